@@ -1,0 +1,166 @@
+/*
+ * hsumma.h -- C ABI of the Hierarchical SUMMA local-update library (gfx950).
+ *
+ * The method (Quintin, Hasanov, Lastovetsky, "Hierarchical Parallel Matrix
+ * Multiplication on Large-Scale Distributed Memory Platforms"): C = A x B on a
+ * virtual P x Q processor grid (the paper's s x t, Sec. II-A), arranged as
+ * I x J groups of (P/I) x (Q/J) processors (Sec. III).  The k dimension is
+ * consumed in outer blocks of width M (the paper's B, "between groups") and
+ * inner blocks of width b <= M ("inside a group"); every processor performs
+ * the local update  C_loc += A_panel x B_panel  once per inner block
+ * (Alg. 1, the DGemm call; Sec. II-A for the update rule c_ij += a_ik b_kj).
+ *
+ * On one GPU every virtual processor is a set of workgroups: its tile of C
+ * is cut into macro-tiles, the processors of one group are steered to one
+ * XCD (one L2), and the two broadcast levels become staging of the outer
+ * panel and LDS streaming of the inner b-slices.  C is held in MFMA
+ * accumulators across all inner steps of one outer step.
+ *
+ * Layout.  A is m x k, B is k x n, C is m x n, all row-major FP64 in device
+ * memory with leading dimensions lda >= k, ldb >= n, ldc >= m's row length n
+ * (elements).  Tiles are views of the global matrices: with the block
+ * distribution a tile is a contiguous sub-block; with the block-cyclic one
+ * it is the set of distribution blocks the processor owns.  Column-major
+ * callers pass transposed problems.
+ *
+ * Ownership.  The caller owns A, B, C and the workspace `ws` (device memory
+ * of at least hsumma_workspace_size() bytes; may be NULL when that size is
+ * 0).  A plan is a host object; on first use on a device it uploads its
+ * work-item table to device memory it allocates and frees in
+ * hsumma_plan_destroy().  Captured HIP graphs are owned by the plan.
+ *
+ * Streams and synchronisation.  `stream` is a hipStream_t passed as void*
+ * (NULL = the null stream).  All compute calls are asynchronous on it and
+ * never synchronise the device.  A, B and C must not alias.
+ *
+ * Errors.  Every int-returning call returns an hsumma_status.  Invalid
+ * arguments return HSUMMA_ERR_INVALID (nothing is launched); HIP failures
+ * return HSUMMA_ERR_DEVICE.  hsumma_last_error() gives a message for the
+ * last failure on the calling thread.  The library never aborts.
+ */
+#ifndef HSUMMA_H
+#define HSUMMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsumma_plan_s* hsumma_plan_t;
+
+typedef enum {
+  HSUMMA_OK = 0,
+  HSUMMA_ERR_INVALID = -1,      /* bad argument or unsupported shape */
+  HSUMMA_ERR_UNSUPPORTED = -2,  /* option not available in this build / device */
+  HSUMMA_ERR_DEVICE = -3,       /* a HIP call failed (message has its text) */
+  HSUMMA_ERR_WORKSPACE = -4     /* workspace missing or too small */
+} hsumma_status;
+
+typedef enum {
+  HSUMMA_FP64 = 0,         /* FP64 MFMA local update */
+  HSUMMA_SPLIT_BF16 = 1,   /* digit split into BF16 slices, FP32-exact MFMA, FP64 recombination */
+  HSUMMA_SPLIT_FP8 = 2     /* the same with FP8-e4m3 slices */
+} hsumma_precision;
+
+typedef enum {
+  HSUMMA_DIST_BLOCK = 0,         /* block-checkerboard distribution (Sec. II-A, Sec. III) */
+  HSUMMA_DIST_BLOCK_CYCLIC = 1   /* block-cyclic distribution (named as future work, Sec. VI) */
+} hsumma_dist;
+
+typedef struct {
+  int64_t m;          /* rows of A and C; 0 => n                                */
+  int64_t k;          /* columns of A = rows of B; 0 => n (Alg. 1's (M, L, N))  */
+  int32_t dist;       /* hsumma_dist                                            */
+  int32_t prec;       /* hsumma_precision                                       */
+  int64_t nb;         /* block-cyclic block size; 0 => b                        */
+  int32_t slices;     /* split forms: digits per operand, 0 => chosen per panel */
+  int32_t min_slices; /* bounds of the per-panel choice; 0 => 3                 */
+  int32_t max_slices; /*                                   0 => 7               */
+  int32_t tile_m;     /* macro-tile rows;  0 => default / tuned                 */
+  int32_t tile_n;     /* macro-tile cols;  0 => default / tuned                 */
+  int32_t kc;         /* k-chunk staged per LDS buffer; 0 => default            */
+  int32_t persistent; /* 1: one grouped persistent launch per step              */
+  int32_t use_graph;  /* 1: hsumma_run replays a captured HIP graph             */
+  int32_t reserved[6];
+} hsumma_opts;
+
+/* Fill *o with defaults (all zero: square, block, FP64, default tiles). */
+void hsumma_opts_default(hsumma_opts* o);
+
+/*
+ * Build a plan for C = A x B with A m x k, B k x n (m, k from opts, else n).
+ * P x Q grid (P <= m, Q <= n), G groups (Sec. III: G = I*J with I | P and
+ * J | Q; the most square arrangement is chosen), inner block b >= 1, outer
+ * block M with b <= M (Sec. III) and M a multiple of b.  G = 1 or G = P*Q is
+ * plain SUMMA (Sec. III).  Host only: validates, builds the step schedule
+ * and the work-item table.  Returns HSUMMA_ERR_INVALID on bad input.
+ */
+int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G,
+                int64_t b, int64_t M, const hsumma_opts* opts);
+void hsumma_plan_destroy(hsumma_plan_t plan);
+
+/* Queries (host only). */
+int hsumma_workspace_size(hsumma_plan_t plan, size_t* bytes);
+int hsumma_num_steps(hsumma_plan_t plan, int64_t* steps);          /* inner steps: ceil(k/b) if M|... */
+int hsumma_num_outer_steps(hsumma_plan_t plan, int64_t* steps);    /* ceil(k/M) */
+int hsumma_groups(hsumma_plan_t plan, int32_t* I, int32_t* J);
+int hsumma_tile_shape(hsumma_plan_t plan, int32_t pr, int32_t pc,
+                      int64_t* m_loc, int64_t* n_loc);
+/*
+ * Step s of the schedule (Alg. 1): its k-range [k0, k1), outer step, and the
+ * owners of its panels: processor column q owning A(:, k0) and processor row
+ * p owning B(k0, :), with their group index and in-group index (the pivot
+ * functions of Alg. 1).
+ */
+int hsumma_step_info(hsumma_plan_t plan, int64_t s, int64_t* k0, int64_t* k1,
+                     int64_t* outer, int32_t* owner_col, int32_t* owner_row,
+                     int32_t* group_col, int32_t* group_row,
+                     int32_t* in_group_col, int32_t* in_group_row);
+/* Number of work items (macro-tiles over all tiles) per launch. */
+int hsumma_num_items(hsumma_plan_t plan, int64_t* items);
+
+/*
+ * One inner step s (0 <= s < num_steps): for every tile,
+ *   C_loc += A(rows, k0:k1) x B(k0:k1, cols)          (Alg. 1, DGemm)
+ * i.e. C += A(:, k0:k1) B(k0:k1, :).  Accumulates into C as given.
+ */
+int hsumma_local_update(hsumma_plan_t plan, int64_t step,
+                        const double* A, int64_t lda, const double* B, int64_t ldb,
+                        double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * One outer step g: all inner steps of the outer block in one launch, C held
+ * in registers across them.  Bitwise equal to the sequence of its
+ * hsumma_local_update calls.  Accumulates into C.
+ */
+int hsumma_outer_update(hsumma_plan_t plan, int64_t outer,
+                        const double* A, int64_t lda, const double* B, int64_t ldb,
+                        double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The whole product C = A x B: every outer step in order (the first one
+ * stores instead of accumulating, so C needs no clearing).  With
+ * opts.use_graph the launch sequence is captured once per (pointers, stream)
+ * and replayed.
+ */
+int hsumma_run(hsumma_plan_t plan, const double* A, int64_t lda, const double* B,
+               int64_t ldb, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* Slice count chosen for each outer panel by the last split-form call
+ * (copied to host; synchronises `stream`).  counts has num_outer_steps room. */
+int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, void* stream);
+
+/* Message for the last failure on this thread ("" if none). */
+const char* hsumma_last_error(void);
+
+/* Library version string. */
+const char* hsumma_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSUMMA_H */

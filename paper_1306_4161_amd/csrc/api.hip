@@ -1,0 +1,490 @@
+// C ABI of the Hierarchical SUMMA local-update library: plans, the step
+// schedule, work-item tables and the launch sequence.
+//
+// Plan (Sec. III, Alg. 1): the P x Q grid is arranged as I x J groups; the
+// k dimension is consumed in outer blocks of M and inner blocks of b.  Each
+// virtual processor's C tile is cut into macro-tiles (work items).  The
+// items are ordered group by group and tile by tile, and that list is cut
+// into 8 contiguous parts, one per XCD: the processors of a group share an
+// L2, the GPU's image of the paper's group-level broadcast.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+
+#include "internal.h"
+
+namespace hs {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace hs
+
+using hs::set_error;
+
+namespace {
+
+struct StepRec {
+  int64_t k0, k1, outer;
+};
+
+struct DeviceState {
+  hs::WorkItem* items = nullptr;
+};
+
+struct GraphKey {
+  const void* A; int64_t lda; const void* B; int64_t ldb; void* C; int64_t ldc;
+  void* ws; void* stream;
+  bool operator==(const GraphKey& o) const {
+    return A == o.A && lda == o.lda && B == o.B && ldb == o.ldb && C == o.C &&
+           ldc == o.ldc && ws == o.ws && stream == o.stream;
+  }
+};
+
+}  // namespace
+
+struct hsumma_plan_s {
+  int64_t m = 0, n = 0, k = 0, b = 0, M = 0, nb = 0;
+  int32_t P = 0, Q = 0, G = 0, I = 0, J = 0;
+  hsumma_opts opts{};
+  hs::TileCfg cfg{};
+  std::vector<int64_t> rlo, clo, kqlo, kplo;  // block-distribution boundaries
+  std::vector<StepRec> steps;
+  std::vector<int64_t> outer_lo;              // k start of each outer step (+ end)
+  std::vector<hs::WorkItem> items;
+  int32_t per_xcd = 0;
+  std::map<int, DeviceState> dev;
+  std::mutex mu;
+  bool have_graph = false;
+  GraphKey gkey{};
+  hipGraphExec_t gexec = nullptr;
+  int gdevice = -1;
+};
+
+namespace {
+
+#define HS_CHECK_HIP(expr)                                                         \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(_e));                \
+      return HSUMMA_ERR_DEVICE;                                                    \
+    }                                                                              \
+  } while (0)
+
+int invalid(const std::string& msg) {
+  set_error(msg);
+  return HSUMMA_ERR_INVALID;
+}
+
+// Most square I x J = G with I | P, J | Q; ties to the smaller I.
+bool factor_groups(int P, int Q, int G, int* I, int* J) {
+  bool found = false;
+  double best_ratio = 0;
+  for (int i = 1; i <= P; ++i) {
+    if (P % i || G % i) continue;
+    int j = G / i;
+    if (j > Q || Q % j) continue;
+    double ratio = (double)std::max(i, j) / (double)std::min(i, j);
+    if (!found || ratio < best_ratio) {
+      found = true;
+      best_ratio = ratio;
+      *I = i;
+      *J = j;
+    }
+  }
+  return found;
+}
+
+// Boundaries of a balanced block split of [0, len) into parts.
+std::vector<int64_t> block_bounds(int64_t len, int parts) {
+  std::vector<int64_t> lo(parts + 1);
+  for (int r = 0; r <= parts; ++r) lo[r] = (int64_t)r * len / parts;
+  return lo;
+}
+
+int owner_block(const std::vector<int64_t>& lo, int64_t g) {
+  // largest r with lo[r] <= g
+  auto it = std::upper_bound(lo.begin(), lo.end(), g);
+  return (int)(it - lo.begin()) - 1;
+}
+
+// Global index runs owned by processor r along one dimension.
+struct Run { int64_t g0, g1; };
+std::vector<Run> runs_of(const hsumma_plan_s& p, bool rows, int r) {
+  std::vector<Run> out;
+  const int64_t len = rows ? p.m : p.n;
+  const int parts = rows ? p.P : p.Q;
+  if (p.opts.dist == HSUMMA_DIST_BLOCK) {
+    const auto& lo = rows ? p.rlo : p.clo;
+    if (lo[r + 1] > lo[r]) out.push_back({lo[r], lo[r + 1]});
+  } else {
+    for (int64_t blk = r; blk * p.nb < len; blk += parts)
+      out.push_back({blk * p.nb, std::min((blk + 1) * p.nb, len)});
+  }
+  return out;
+}
+
+int64_t local_count(const hsumma_plan_s& p, bool rows, int r) {
+  int64_t c = 0;
+  for (auto& run : runs_of(p, rows, r)) c += run.g1 - run.g0;
+  return c;
+}
+
+void build_items(hsumma_plan_s& p) {
+  const int gp = p.P / p.I, gq = p.Q / p.J;
+  std::vector<std::vector<Run>> rpieces(p.P), cpieces(p.Q);
+  for (int r = 0; r < p.P; ++r)
+    for (auto& run : runs_of(p, true, r))
+      for (int64_t g = run.g0; g < run.g1; g += p.cfg.tm)
+        rpieces[r].push_back({g, std::min(g + p.cfg.tm, run.g1)});
+  for (int c = 0; c < p.Q; ++c)
+    for (auto& run : runs_of(p, false, c))
+      for (int64_t g = run.g0; g < run.g1; g += p.cfg.tn)
+        cpieces[c].push_back({g, std::min(g + p.cfg.tn, run.g1)});
+  p.items.clear();
+  for (int x = 0; x < p.I; ++x)
+    for (int y = 0; y < p.J; ++y)
+      for (int i = 0; i < gp; ++i)
+        for (int j = 0; j < gq; ++j) {
+          const int pr = x * gp + i, pc = y * gq + j;
+          for (auto& rp : rpieces[pr])
+            for (auto& cp : cpieces[pc])
+              p.items.push_back({(int32_t)rp.g0, (int32_t)cp.g0, (int32_t)(rp.g1 - rp.g0),
+                                 (int32_t)(cp.g1 - cp.g0)});
+        }
+  const int64_t nit = (int64_t)p.items.size();
+  p.per_xcd = (int32_t)((nit + 7) / 8);
+  if (p.opts.persistent) {
+    // Longest-processing-time order inside each XCD's list, so that the
+    // static round-robin of the persistent workgroups stays balanced when
+    // tiles are uneven (ragged block-cyclic edges).
+    for (int x = 0; x < 8; ++x) {
+      auto b0 = p.items.begin() + std::min<int64_t>(nit, (int64_t)x * p.per_xcd);
+      auto b1 = p.items.begin() + std::min<int64_t>(nit, (int64_t)(x + 1) * p.per_xcd);
+      std::stable_sort(b0, b1, [](const hs::WorkItem& a, const hs::WorkItem& b) {
+        return (int64_t)a.h * a.w > (int64_t)b.h * b.w;
+      });
+    }
+  }
+}
+
+int ensure_device(hsumma_plan_t p, hs::WorkItem** items) {
+  int dev = 0;
+  HS_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(p->mu);
+  auto it = p->dev.find(dev);
+  if (it != p->dev.end()) {
+    *items = it->second.items;
+    return HSUMMA_OK;
+  }
+  DeviceState st;
+  const size_t bytes = std::max<size_t>(1, p->items.size()) * sizeof(hs::WorkItem);
+  HS_CHECK_HIP(hipMalloc((void**)&st.items, bytes));
+  if (!p->items.empty()) {
+    hipError_t e = hipMemcpy(st.items, p->items.data(), p->items.size() * sizeof(hs::WorkItem),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      hipFree(st.items);
+      set_error(std::string("hipMemcpy(work items): ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+  }
+  p->dev[dev] = st;
+  *items = st.items;
+  return HSUMMA_OK;
+}
+
+int check_operands(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                   double* C, int64_t ldc) {
+  if (!p) return invalid("null plan");
+  if (!C || (p->k > 0 && (!A || !B))) return invalid("null matrix pointer");
+  if (lda < std::max<int64_t>(1, p->k) || ldb < p->n || ldc < p->n)
+    return invalid("leading dimension smaller than the row length");
+  if (((uintptr_t)A | (uintptr_t)B | (uintptr_t)C) & 7)
+    return invalid("matrix pointers must be 8-byte aligned");
+  return HSUMMA_OK;
+}
+
+// Launch the update kernel over k-range [k0, k1) (starting at an inner-step
+// boundary) for every work item.
+int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init,
+                 hipStream_t stream) {
+  if (p->opts.prec != HSUMMA_FP64) {
+    set_error("precision form not available in this build");
+    return HSUMMA_ERR_UNSUPPORTED;
+  }
+  hs::WorkItem* items = nullptr;
+  int rc = ensure_device(p, &items);
+  if (rc) return rc;
+  if (p->items.empty()) return HSUMMA_OK;
+  hs::UpdateArgs a;
+  a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
+  a.items = items; a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;
+  a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
+  a.persistent = p->opts.persistent;
+  int grid = 8 * p->per_xcd;
+  if (p->opts.persistent) {
+    int dev = 0, cus = 0;
+    HS_CHECK_HIP(hipGetDevice(&dev));
+    HS_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int occ = std::max(1, hs::fp64_occupancy(p->cfg));
+    grid = std::min<int64_t>(grid, (int64_t)cus * occ);
+    grid = std::max(8, (grid / 8) * 8);
+  }
+  hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream);
+  if (e != hipSuccess) {
+    set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
+  }
+  return HSUMMA_OK;
+}
+
+int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+               double* C, int64_t ldc, hipStream_t stream) {
+  const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
+  if (nouter <= 0)  // k == 0: C = 0
+    return launch_range(p, A, lda, B, ldb, C, ldc, 0, 0, 1, stream);
+  for (int64_t g = 0; g < nouter; ++g) {
+    int rc = launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[g], p->outer_lo[g + 1],
+                          g == 0 ? 1 : 0, stream);
+    if (rc) return rc;
+  }
+  return HSUMMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hsumma_opts_default(hsumma_opts* o) {
+  if (o) std::memset(o, 0, sizeof(*o));
+}
+
+const char* hsumma_last_error(void) { return hs::g_last_error.c_str(); }
+
+const char* hsumma_version(void) { return "hsumma-gfx950 0.1"; }
+
+int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, int64_t b,
+                int64_t M, const hsumma_opts* opts) {
+  if (!out) return invalid("null output pointer");
+  *out = nullptr;
+  hsumma_opts o;
+  hsumma_opts_default(&o);
+  if (opts) o = *opts;
+  const int64_t m = o.m ? o.m : n;
+  const int64_t k = o.k ? o.k : n;
+  if (n < 1 || m < 1 || k < 0 || o.m < 0 || o.k < 0) return invalid("matrix sizes must be positive");
+  if (m >= (1LL << 31) || n >= (1LL << 31)) return invalid("m and n must be below 2^31");
+  if (P < 1 || Q < 1) return invalid("P and Q must be >= 1");
+  if (P > m || Q > n) return invalid("grid larger than the matrix (need P <= m, Q <= n)");
+  if (G < 1) return invalid("G must be >= 1");
+  if (b < 1) return invalid("b must be >= 1");
+  if (M < b) return invalid("outer block M must be >= inner block b");
+  if (M % b) return invalid("outer block M must be a multiple of b");
+  if (o.dist != HSUMMA_DIST_BLOCK && o.dist != HSUMMA_DIST_BLOCK_CYCLIC)
+    return invalid("unknown distribution");
+  if (o.prec != HSUMMA_FP64 && o.prec != HSUMMA_SPLIT_BF16 && o.prec != HSUMMA_SPLIT_FP8)
+    return invalid("unknown precision");
+  if (o.nb < 0) return invalid("nb must be >= 0");
+  int I = 0, J = 0;
+  if (!factor_groups(P, Q, G, &I, &J))
+    return invalid("G cannot be arranged as I x J groups with I | P and J | Q");
+
+  hsumma_plan_s* p = new (std::nothrow) hsumma_plan_s();
+  if (!p) return invalid("out of host memory");
+  p->m = m; p->n = n; p->k = k; p->b = b; p->M = M;
+  p->nb = o.nb ? o.nb : b;
+  p->P = P; p->Q = Q; p->G = G; p->I = I; p->J = J;
+  p->opts = o;
+  p->opts.m = m; p->opts.k = k; p->opts.nb = p->nb;
+
+  // Tile configuration.
+  hs::TileCfg cfg{o.tile_m ? o.tile_m : 128, o.tile_n ? o.tile_n : 128, o.kc ? o.kc : 16};
+  if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) cfg = {64, 64, 16};
+  bool ok = false;
+  for (auto& c : hs::fp64_configs())
+    if (c.tm == cfg.tm && c.tn == cfg.tn && c.kc == cfg.kc) ok = true;
+  if (!ok) {
+    delete p;
+    return invalid("tile configuration (tile_m, tile_n, kc) not compiled into the library");
+  }
+  p->cfg = cfg;
+
+  p->rlo = block_bounds(m, P);
+  p->clo = block_bounds(n, Q);
+  p->kqlo = block_bounds(k, Q);
+  p->kplo = block_bounds(k, P);
+  for (int64_t g0 = 0; g0 < k; g0 += M) {
+    const int64_t g1 = std::min(g0 + M, k);
+    p->outer_lo.push_back(g0);
+    for (int64_t s0 = g0; s0 < g1; s0 += b)
+      p->steps.push_back({s0, std::min(s0 + b, g1), (int64_t)p->outer_lo.size() - 1});
+  }
+  p->outer_lo.push_back(k);
+  if (k == 0) p->outer_lo.assign(1, 0);
+  build_items(*p);
+  *out = p;
+  return HSUMMA_OK;
+}
+
+void hsumma_plan_destroy(hsumma_plan_t p) {
+  if (!p) return;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  for (auto& kv : p->dev) {
+    if (hipSetDevice(kv.first) == hipSuccess) hipFree(kv.second.items);
+  }
+  if (cur >= 0) hipSetDevice(cur);
+  delete p;
+}
+
+int hsumma_workspace_size(hsumma_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return invalid("null argument");
+  *bytes = 0;
+  return HSUMMA_OK;
+}
+
+int hsumma_num_steps(hsumma_plan_t p, int64_t* steps) {
+  if (!p || !steps) return invalid("null argument");
+  *steps = (int64_t)p->steps.size();
+  return HSUMMA_OK;
+}
+
+int hsumma_num_outer_steps(hsumma_plan_t p, int64_t* steps) {
+  if (!p || !steps) return invalid("null argument");
+  *steps = (int64_t)p->outer_lo.size() - 1;
+  return HSUMMA_OK;
+}
+
+int hsumma_groups(hsumma_plan_t p, int32_t* I, int32_t* J) {
+  if (!p || !I || !J) return invalid("null argument");
+  *I = p->I;
+  *J = p->J;
+  return HSUMMA_OK;
+}
+
+int hsumma_num_items(hsumma_plan_t p, int64_t* items) {
+  if (!p || !items) return invalid("null argument");
+  *items = (int64_t)p->items.size();
+  return HSUMMA_OK;
+}
+
+int hsumma_tile_shape(hsumma_plan_t p, int32_t pr, int32_t pc, int64_t* m_loc, int64_t* n_loc) {
+  if (!p || !m_loc || !n_loc) return invalid("null argument");
+  if (pr < 0 || pr >= p->P || pc < 0 || pc >= p->Q) return invalid("processor index out of range");
+  *m_loc = local_count(*p, true, pr);
+  *n_loc = local_count(*p, false, pc);
+  return HSUMMA_OK;
+}
+
+int hsumma_step_info(hsumma_plan_t p, int64_t s, int64_t* k0, int64_t* k1, int64_t* outer,
+                     int32_t* owner_col, int32_t* owner_row, int32_t* group_col,
+                     int32_t* group_row, int32_t* in_group_col, int32_t* in_group_row) {
+  if (!p) return invalid("null plan");
+  if (s < 0 || s >= (int64_t)p->steps.size()) return invalid("step out of range");
+  const StepRec& st = p->steps[s];
+  int q, r;
+  if (p->opts.dist == HSUMMA_DIST_BLOCK) {
+    q = owner_block(p->kqlo, st.k0);
+    r = owner_block(p->kplo, st.k0);
+  } else {
+    q = (int)((st.k0 / p->nb) % p->Q);
+    r = (int)((st.k0 / p->nb) % p->P);
+  }
+  const int gq = p->Q / p->J, gp = p->P / p->I;
+  if (k0) *k0 = st.k0;
+  if (k1) *k1 = st.k1;
+  if (outer) *outer = st.outer;
+  if (owner_col) *owner_col = q;
+  if (owner_row) *owner_row = r;
+  if (group_col) *group_col = q / gq;
+  if (group_row) *group_row = r / gp;
+  if (in_group_col) *in_group_col = q % gq;
+  if (in_group_row) *in_group_row = r % gp;
+  return HSUMMA_OK;
+}
+
+int hsumma_local_update(hsumma_plan_t p, int64_t step, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* C, int64_t ldc, void* ws,
+                        size_t ws_bytes, void* stream) {
+  int rc = check_operands(p, A, lda, B, ldb, C, ldc);
+  if (rc) return rc;
+  if (step < 0 || step >= (int64_t)p->steps.size()) return invalid("step out of range");
+  (void)ws; (void)ws_bytes;
+  const StepRec& st = p->steps[step];
+  return launch_range(p, A, lda, B, ldb, C, ldc, st.k0, st.k1, 0, (hipStream_t)stream);
+}
+
+int hsumma_outer_update(hsumma_plan_t p, int64_t outer, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* C, int64_t ldc, void* ws,
+                        size_t ws_bytes, void* stream) {
+  int rc = check_operands(p, A, lda, B, ldb, C, ldc);
+  if (rc) return rc;
+  if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
+  (void)ws; (void)ws_bytes;
+  return launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1], 0,
+                      (hipStream_t)stream);
+}
+
+int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+               double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_operands(p, A, lda, B, ldb, C, ldc);
+  if (rc) return rc;
+  (void)ws_bytes;
+  hipStream_t s = (hipStream_t)stream;
+  if (!p->opts.use_graph || s == nullptr) return run_direct(p, A, lda, B, ldb, C, ldc, s);
+
+  // Graph mode: capture the launch sequence once per (pointers, stream).
+  hs::WorkItem* items = nullptr;
+  rc = ensure_device(p, &items);  // allocation must happen outside the capture
+  if (rc) return rc;
+  int dev = 0;
+  HS_CHECK_HIP(hipGetDevice(&dev));
+  GraphKey key{A, lda, B, ldb, C, ldc, ws, stream};
+  if (!(p->have_graph && p->gkey == key && p->gdevice == dev)) {
+    if (p->gexec) {
+      hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+      p->have_graph = false;
+    }
+    HS_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc2) {
+      if (graph) hipGraphDestroy(graph);
+      return rc2;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+    e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      p->gexec = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+    p->gkey = key;
+    p->gdevice = dev;
+    p->have_graph = true;
+  }
+  HS_CHECK_HIP(hipGraphLaunch(p->gexec, s));
+  return HSUMMA_OK;
+}
+
+int hsumma_panel_slices(hsumma_plan_t p, const void* ws, int32_t* counts, void* stream) {
+  (void)ws; (void)counts; (void)stream;
+  if (!p) return invalid("null plan");
+  set_error("no split-form panel in this plan");
+  return HSUMMA_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hsumma.h"
+
+namespace hs {
+
+// One rectangle of C that one workgroup updates: rows [r0, r0+h) and
+// columns [c0, c0+w) of the global row-major matrix.  It lies inside one
+// virtual processor's tile (and, for the block-cyclic distribution, inside
+// one distribution block), so it is a macro-tile of that processor's local
+// update.
+struct WorkItem {
+  int32_t r0, c0, h, w;
+};
+
+// Arguments common to the update kernels of one launch.
+struct UpdateArgs {
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  double* C; int64_t ldc;
+  const WorkItem* items; int32_t nitems; int32_t per_xcd;
+  int64_t k0, k1;      // k-range of this launch (starts at a step boundary)
+  int64_t bstep;       // inner block b: quads restart at every step start
+  int32_t zero_init;   // 1: start from C = 0 instead of loading C
+  int32_t persistent;  // 1: grid-stride over the items (grouped persistent mode)
+};
+
+// Kernel configurations (macro-tile and k-chunk) compiled into the library.
+struct TileCfg { int tm, tn, kc; };
+const std::vector<TileCfg>& fp64_configs();
+hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s);
+int fp64_occupancy(const TileCfg& cfg);  // workgroups per CU the config is built for
+
+// Split (precision) path.
+struct SplitArgs;
+struct SliceArgs;
+
+void set_error(const std::string& msg);
+
+}  // namespace hs

@@ -1,0 +1,231 @@
+"""ctypes binding of libhsumma.so (the C ABI declared in include/hsumma.h).
+
+Argument marshalling only: every step of the local update runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.
+If the library is missing the first call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsumma.so")
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_WORKSPACE = 0, -1, -2, -3, -4
+FP64, SPLIT_BF16, SPLIT_FP8 = 0, 1, 2
+DIST_BLOCK, DIST_BLOCK_CYCLIC = 0, 1
+
+EXPORTED = [
+    "hsumma_opts_default", "hsumma_plan", "hsumma_plan_destroy", "hsumma_workspace_size",
+    "hsumma_num_steps", "hsumma_num_outer_steps", "hsumma_groups", "hsumma_tile_shape",
+    "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
+    "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
+]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("dist", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("nb", ctypes.c_int64),
+        ("slices", ctypes.c_int32), ("min_slices", ctypes.c_int32), ("max_slices", ctypes.c_int32),
+        ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32), ("kc", ctypes.c_int32),
+        ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class HsummaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hsumma error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libhsumma.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhsumma.so not built: run `python -m paper_1306_4161_amd.build` "
+                               "(the HIP library is required; there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        P = ctypes.POINTER
+        L.hsumma_opts_default.argtypes = [P(Opts)]
+        L.hsumma_opts_default.restype = None
+        L.hsumma_plan.argtypes = [P(vp), i64, i32, i32, i32, i64, i64, P(Opts)]
+        L.hsumma_plan_destroy.argtypes = [vp]
+        L.hsumma_plan_destroy.restype = None
+        L.hsumma_workspace_size.argtypes = [vp, P(ctypes.c_size_t)]
+        L.hsumma_num_steps.argtypes = [vp, P(i64)]
+        L.hsumma_num_outer_steps.argtypes = [vp, P(i64)]
+        L.hsumma_num_items.argtypes = [vp, P(i64)]
+        L.hsumma_groups.argtypes = [vp, P(i32), P(i32)]
+        L.hsumma_tile_shape.argtypes = [vp, i32, i32, P(i64), P(i64)]
+        L.hsumma_step_info.argtypes = [vp, i64, P(i64), P(i64), P(i64), P(i32), P(i32),
+                                       P(i32), P(i32), P(i32), P(i32)]
+        upd = [vp, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        L.hsumma_local_update.argtypes = upd
+        L.hsumma_outer_update.argtypes = upd
+        L.hsumma_run.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        L.hsumma_panel_slices.argtypes = [vp, vp, P(i32), vp]
+        L.hsumma_last_error.restype = ctypes.c_char_p
+        L.hsumma_last_error.argtypes = []
+        L.hsumma_version.restype = ctypes.c_char_p
+        L.hsumma_version.argtypes = []
+        for name in EXPORTED:
+            if name not in ("hsumma_opts_default", "hsumma_plan_destroy",
+                            "hsumma_last_error", "hsumma_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise HsummaError(rc, lib().hsumma_last_error().decode())
+
+
+def _dev_ptr(t, what):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % what)
+    if t.device.type != "cuda":
+        raise ValueError("%s must live on the GPU" % what)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % what)
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be a 2-D row-major view (unit column stride)" % what)
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Host plan for C = A x B on a virtual P x Q grid with G groups."""
+
+    def __init__(self, n, P, Q, G, b, M=None, *, m=0, k=0, dist=DIST_BLOCK, nb=0,
+                 prec=FP64, slices=0, min_slices=0, max_slices=0, tile_m=0, tile_n=0,
+                 kc=0, persistent=0, use_graph=0):
+        L = lib()
+        o = Opts()
+        L.hsumma_opts_default(ctypes.byref(o))
+        o.m, o.k, o.dist, o.nb, o.prec = m, k, dist, nb, prec
+        o.slices, o.min_slices, o.max_slices = slices, min_slices, max_slices
+        o.tile_m, o.tile_n, o.kc = tile_m, tile_n, kc
+        o.persistent, o.use_graph = persistent, use_graph
+        h = ctypes.c_void_p()
+        _check(L.hsumma_plan(ctypes.byref(h), n, P, Q, G, b, M if M is not None else b,
+                             ctypes.byref(o)))
+        self._h = h
+        self.n, self.m, self.k = n, (m or n), (k or n)
+        self.P, self.Q, self.G, self.b = P, Q, G, b
+        self.M = M if M is not None else b
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hsumma_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- queries ---------------------------------------------------------
+    def _i64(self, fn):
+        v = ctypes.c_int64()
+        _check(fn(self._h, ctypes.byref(v)))
+        return v.value
+
+    @property
+    def num_steps(self):
+        return self._i64(lib().hsumma_num_steps)
+
+    @property
+    def num_outer_steps(self):
+        return self._i64(lib().hsumma_num_outer_steps)
+
+    @property
+    def num_items(self):
+        return self._i64(lib().hsumma_num_items)
+
+    @property
+    def workspace_size(self):
+        v = ctypes.c_size_t()
+        _check(lib().hsumma_workspace_size(self._h, ctypes.byref(v)))
+        return v.value
+
+    @property
+    def groups(self):
+        I, J = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().hsumma_groups(self._h, ctypes.byref(I), ctypes.byref(J)))
+        return I.value, J.value
+
+    def tile_shape(self, pr, pc):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hsumma_tile_shape(self._h, pr, pc, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def step_info(self, s):
+        v64 = [ctypes.c_int64() for _ in range(3)]
+        v32 = [ctypes.c_int32() for _ in range(6)]
+        _check(lib().hsumma_step_info(self._h, s, *[ctypes.byref(x) for x in v64],
+                                      *[ctypes.byref(x) for x in v32]))
+        keys = ["k0", "k1", "outer", "owner_col", "owner_row", "group_col", "group_row",
+                "in_group_col", "in_group_row"]
+        return dict(zip(keys, [x.value for x in v64 + v32]))
+
+    # ---- compute ---------------------------------------------------------
+    def workspace(self):
+        import torch
+        nbytes = self.workspace_size
+        if nbytes == 0:
+            return None
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def _args(self, A, B, C, ws):
+        a, lda = _dev_ptr(A, "A")
+        b, ldb = _dev_ptr(B, "B")
+        c, ldc = _dev_ptr(C, "C")
+        if tuple(A.shape) != (self.m, self.k) or tuple(B.shape) != (self.k, self.n) \
+                or tuple(C.shape) != (self.m, self.n):
+            raise ValueError("operand shapes do not match the plan")
+        wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
+        wsn = ws.numel() * ws.element_size() if ws is not None else 0
+        return a, lda, b, ldb, c, ldc, wsp, wsn
+
+    def local_update(self, step, A, B, C, ws=None, stream=None):
+        a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)
+        _check(lib().hsumma_local_update(self._h, step, a, lda, b, ldb, c, ldc, wsp, wsn,
+                                         _stream(stream)))
+
+    def outer_update(self, g, A, B, C, ws=None, stream=None):
+        a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)
+        _check(lib().hsumma_outer_update(self._h, g, a, lda, b, ldb, c, ldc, wsp, wsn,
+                                         _stream(stream)))
+
+    def run(self, A, B, C, ws=None, stream=None):
+        a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)
+        _check(lib().hsumma_run(self._h, a, lda, b, ldb, c, ldc, wsp, wsn, _stream(stream)))
+
+    def panel_slices(self, ws, stream=None):
+        n = self.num_outer_steps
+        out = (ctypes.c_int32 * n)()
+        _check(lib().hsumma_panel_slices(self._h, ctypes.c_void_p(ws.data_ptr()), out,
+                                         _stream(stream)))
+        return list(out)
+
+
+def version():
+    return lib().hsumma_version().decode()

@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI: exported symbols, validation, plan math.
+
+No GPU needed: plan creation and queries are host-only.  The plan's step
+schedule, owner map, grouping and tile shapes are compared with the oracle's
+independent plan reference (oracle/plan_ref.py).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import plan_ref
+from paper_1306_4161_amd import hsumma as hs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(hsumma_\w+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(hs.LIB_PATH)
+    declared = _declared_functions()
+    assert "hsumma_plan" in declared and "hsumma_local_update" in declared
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(hs.EXPORTED) <= declared | {"hsumma_opts_default"}
+
+
+def test_version():
+    assert hs.version().startswith("hsumma-gfx950")
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((100, 4, 4, 3, 8, 8), "cannot be arranged"),
+    ((100, 4, 4, 1, 0, 8), "b must be"),
+    ((100, 4, 4, 1, 16, 8), "M must be >="),
+    ((100, 4, 4, 1, 16, 24), "multiple of b"),
+    ((3, 4, 1, 1, 1, 1), "grid larger"),
+    ((0, 1, 1, 1, 1, 1), "positive"),
+    ((64, 2, 3, 4, 8, 8), "cannot be arranged"),
+])
+def test_plan_rejects_invalid(args, msg):
+    with pytest.raises(hs.HsummaError) as ei:
+        hs.Plan(*args)
+    assert ei.value.code == hs.ERR_INVALID
+    assert msg in str(ei.value)
+
+
+def test_plan_rejects_unknown_tile_and_enum():
+    with pytest.raises(hs.HsummaError):
+        hs.Plan(256, 2, 2, 1, 32, tile_m=96, tile_n=96)
+    with pytest.raises(hs.HsummaError):
+        hs.Plan(256, 2, 2, 1, 32, dist=7)
+    with pytest.raises(hs.HsummaError):
+        hs.Plan(256, 2, 2, 1, 32, prec=9)
+
+
+PLAN_CASES = [
+    # n, P, Q, G, b, M, dist, nb, m, k
+    (256, 2, 2, 1, 32, 32, "block", 0, 0, 0),
+    (8192, 8, 8, 4, 64, 256, "block", 0, 0, 0),
+    (16384, 16, 16, 16, 256, 256, "block", 0, 0, 0),
+    (10000, 6, 10, 1, 128, 128, "cyclic", 128, 0, 0),
+    (1000, 6, 6, 9, 20, 40, "block", 0, 0, 0),
+    (77, 3, 5, 15, 6, 12, "cyclic", 5, 91, 53),
+    (130, 4, 3, 6, 7, 21, "block", 0, 65, 200),
+]
+
+
+@pytest.mark.parametrize("case", PLAN_CASES)
+def test_plan_matches_reference(case):
+    n, P, Q, G, b, M, dist, nb, m, k = case
+    d = hs.DIST_BLOCK if dist == "block" else hs.DIST_BLOCK_CYCLIC
+    p = hs.Plan(n, P, Q, G, b, M, dist=d, nb=nb, m=m, k=k)
+    m = m or n
+    k = k or n
+    nbe = nb or b
+    assert p.groups == plan_ref.factor_groups(P, Q, G)
+    ref_steps = plan_ref.steps(k, b, M)
+    assert p.num_steps == len(ref_steps)
+    assert p.num_outer_steps == len({s.outer for s in ref_steps})
+    I, J = p.groups
+    gp, gq = P // I, Q // J
+    for s in ref_steps[:: max(1, len(ref_steps) // 50)] + ref_steps[-2:]:
+        info = p.step_info(s.index)
+        assert (info["k0"], info["k1"], info["outer"]) == (s.k0, s.k1, s.outer)
+        q = plan_ref.owner(s.k0, k, Q, dist, nbe)
+        r = plan_ref.owner(s.k0, k, P, dist, nbe)
+        assert info["owner_col"] == q and info["owner_row"] == r
+        assert (info["group_col"], info["in_group_col"]) == (q // gq, q % gq)
+        assert (info["group_row"], info["in_group_row"]) == (r // gp, r % gp)
+    if m * n <= 10 ** 8:
+        shapes = plan_ref.tile_shapes(m, n, P, Q, dist, nbe) if m * n < 4 * 10 ** 6 else None
+        for pr in range(P):
+            for pc in range(Q):
+                got = p.tile_shape(pr, pc)
+                if shapes is not None:
+                    assert got == shapes[(pr, pc)]
+                else:
+                    assert got == (len(plan_ref.local_indices(m, P, pr, dist, nbe)),
+                                   len(plan_ref.local_indices(n, Q, pc, dist, nbe)))
+    p.close()
+
+
+def test_cyclic_tiles_of_the_6x10_grid():
+    p = hs.Plan(10000, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC)
+    rows = {p.tile_shape(r, 0)[0] for r in range(6)}
+    cols = {p.tile_shape(0, c)[1] for c in range(10)}
+    assert rows == {1680, 1664} and cols == {1024, 912, 896}
+    assert p.num_steps == 79
+    assert p.step_info(78)["k1"] - p.step_info(78)["k0"] == 16
+
+
+def test_queries_reject_bad_indices():
+    p = hs.Plan(64, 2, 2, 1, 8)
+    with pytest.raises(hs.HsummaError):
+        p.step_info(8)
+    with pytest.raises(hs.HsummaError):
+        p.tile_shape(2, 0)
+    assert p.workspace_size == 0
