@@ -83,7 +83,9 @@ typedef struct {
   int32_t kc;         /* k-chunk staged per LDS buffer; 0 => default            */
   int32_t persistent; /* 1: one grouped persistent launch per step              */
   int32_t use_graph;  /* 1: hsumma_run replays a captured HIP graph             */
-  int32_t reserved[6];
+  int32_t tau_bits;   /* split forms, per-panel slice choice: target bits of    */
+                      /* accuracy relative to (|A||B|)_ij; 0 => 51              */
+  int32_t reserved[5];
 } hsumma_opts;
 
 /* Fill *o with defaults (all zero: square, block, FP64, default tiles). */
@@ -152,6 +154,28 @@ int hsumma_run(hsumma_plan_t plan, const double* A, int64_t lda, const double* B
 /* Slice count chosen for each outer panel by the last split-form call
  * (copied to host; synchronises `stream`).  counts has num_outer_steps room. */
 int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, void* stream);
+
+/*
+ * Layout of the split forms' workspace after a call: byte offsets of the A
+ * digit planes (planes x m x Wp digits, row-major, 2 B per BF16 digit or 1 B
+ * per FP8-e4m3 digit), the B digit planes (planes x n x Wp, B transposed:
+ * row j holds column j of the panel), the int32 row exponents of A and
+ * column exponents of B.  They hold the most recently split panel.  Lets a
+ * caller inspect the split; HSUMMA_ERR_UNSUPPORTED for the FP64 path.
+ */
+int hsumma_split_layout(hsumma_plan_t plan, size_t* off_digA, size_t* off_digB,
+                        size_t* off_eA, size_t* off_fB, int32_t* Wp, int32_t* planes);
+
+/*
+ * Self-test of the matrix-core accumulation the split forms rely on:
+ * d (16 x 16 FP32, row-major) = a (16 x k digits, row-major) x b (k x 16
+ * digits, row-major) by chained 16x16x32 MFMAs with FP32 accumulation,
+ * fmt 0 = BF16 bit patterns (2 B), 1 = FP8-e4m3 bytes.  k a multiple of 32.
+ * Integer digits whose partial sums stay within 2^24 must come back exact.
+ * All pointers are device memory; asynchronous on `stream`.
+ */
+int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k, float* d,
+                            void* stream);
 
 /* Message for the last failure on this thread ("" if none). */
 const char* hsumma_last_error(void);

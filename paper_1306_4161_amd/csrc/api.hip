@@ -15,6 +15,7 @@
 #include <new>
 
 #include "internal.h"
+#include "split.h"
 
 namespace hs {
 
@@ -56,6 +57,11 @@ struct hsumma_plan_s {
   std::vector<int64_t> outer_lo;              // k start of each outer step (+ end)
   std::vector<hs::WorkItem> items;
   int32_t per_xcd = 0;
+  // precision form: workspace layout (byte offsets) and panel geometry
+  int32_t fmt = -1;            // -1: FP64 path; 0: BF16 digits; 1: FP8-e4m3 digits
+  int32_t Wp = 0;              // padded panel width
+  size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_stats = 0, off_slices = 0,
+         ws_bytes = 0;
   std::map<int, DeviceState> dev;
   std::mutex mu;
   bool have_graph = false;
@@ -210,48 +216,91 @@ int check_operands(hsumma_plan_t p, const double* A, int64_t lda, const double* 
 }
 
 // Launch the update kernel over k-range [k0, k1) (starting at an inner-step
-// boundary) for every work item.
+// boundary) for every work item.  `slot` indexes the per-panel statistics of
+// the precision form.
 int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
-                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init,
-                 hipStream_t stream) {
-  if (p->opts.prec != HSUMMA_FP64) {
-    set_error("precision form not available in this build");
-    return HSUMMA_ERR_UNSUPPORTED;
-  }
+                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init, int64_t slot,
+                 void* ws, size_t ws_bytes, hipStream_t stream) {
   hs::WorkItem* items = nullptr;
   int rc = ensure_device(p, &items);
   if (rc) return rc;
   if (p->items.empty()) return HSUMMA_OK;
-  hs::UpdateArgs a;
-  a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
-  a.items = items; a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;
-  a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
-  a.persistent = p->opts.persistent;
   int grid = 8 * p->per_xcd;
   if (p->opts.persistent) {
     int dev = 0, cus = 0;
     HS_CHECK_HIP(hipGetDevice(&dev));
     HS_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int occ = std::max(1, hs::fp64_occupancy(p->cfg));
+    const int occ = p->fmt < 0 ? std::max(1, hs::fp64_occupancy(p->cfg)) : 1;
     grid = std::min<int64_t>(grid, (int64_t)cus * occ);
     grid = std::max(8, (grid / 8) * 8);
   }
-  hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream);
+  if (p->fmt < 0) {
+    hs::UpdateArgs a;
+    a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
+    a.items = items; a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;
+    a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
+    a.persistent = p->opts.persistent;
+    hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream);
+    if (e != hipSuccess) {
+      set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+    return HSUMMA_OK;
+  }
+  // ---- precision form: split the panel, then slice products ----------------
+  if (!ws || ws_bytes < p->ws_bytes) {
+    set_error("workspace missing or smaller than hsumma_workspace_size()");
+    return HSUMMA_ERR_WORKSPACE;
+  }
+  if (((uintptr_t)ws) & 255) return invalid("workspace must be 256-byte aligned");
+  uint8_t* w8 = (uint8_t*)ws;
+  uint32_t* stats = (uint32_t*)(w8 + p->off_stats) + 2 * slot;
+  hipError_t e = hs::launch_zero_u32(stats, 2, stream);
   if (e != hipSuccess) {
-    set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));
+    set_error(std::string("stats clear: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
+  }
+  const int esz = p->fmt == 0 ? 2 : 1;
+  (void)esz;
+  hs::SplitArgs sa;
+  sa.A = A; sa.lda = lda; sa.B = B; sa.ldb = ldb;
+  sa.m = (int32_t)p->m; sa.n = (int32_t)p->n; sa.k0 = (int32_t)k0; sa.w = (int32_t)(k1 - k0);
+  sa.Wp = (int32_t)(((k1 - k0) + hs::kSplitChunk - 1) / hs::kSplitChunk * hs::kSplitChunk);
+  sa.fmt = p->fmt;
+  sa.smax = p->opts.max_slices;
+  sa.digA = w8 + p->off_digA; sa.planeA = (int64_t)p->m * sa.Wp;
+  sa.digB = w8 + p->off_digB; sa.planeB = (int64_t)p->n * sa.Wp;
+  sa.eA = (int32_t*)(w8 + p->off_eA); sa.fB = (int32_t*)(w8 + p->off_fB);
+  sa.stats = stats;
+  e = hs::launch_split(sa, stream);
+  if (e != hipSuccess) {
+    set_error(std::string("split launch: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
+  }
+  hs::SliceArgs la;
+  la.digA = sa.digA; la.planeA = sa.planeA; la.digB = sa.digB; la.planeB = sa.planeB;
+  la.eA = sa.eA; la.fB = sa.fB; la.stats = stats;
+  la.slices_out = (int32_t*)(w8 + p->off_slices) + slot;
+  la.C = C; la.ldc = ldc;
+  la.items = items; la.nitems = (int32_t)p->items.size(); la.per_xcd = p->per_xcd;
+  la.Wp = sa.Wp; la.nchunks = sa.Wp / hs::kSplitChunk;
+  la.fixed_s = p->opts.slices; la.smin = p->opts.min_slices; la.smax = p->opts.max_slices;
+  la.tau_bits = p->opts.tau_bits;
+  la.zero_init = zero_init; la.persistent = p->opts.persistent;
+  e = hs::launch_slices(p->fmt, la, grid, stream);
+  if (e != hipSuccess) {
+    set_error(std::string("slice products launch: ") + hipGetErrorString(e));
     return HSUMMA_ERR_DEVICE;
   }
   return HSUMMA_OK;
 }
 
 int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
-               double* C, int64_t ldc, hipStream_t stream) {
+               double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
   const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
-  if (nouter <= 0)  // k == 0: C = 0
-    return launch_range(p, A, lda, B, ldb, C, ldc, 0, 0, 1, stream);
   for (int64_t g = 0; g < nouter; ++g) {
     int rc = launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[g], p->outer_lo[g + 1],
-                          g == 0 ? 1 : 0, stream);
+                          g == 0 ? 1 : 0, g, ws, ws_bytes, stream);
     if (rc) return rc;
   }
   return HSUMMA_OK;
@@ -304,16 +353,57 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   p->opts.m = m; p->opts.k = k; p->opts.nb = p->nb;
 
   // Tile configuration.
-  hs::TileCfg cfg{o.tile_m ? o.tile_m : 128, o.tile_n ? o.tile_n : 128, o.kc ? o.kc : 16};
-  if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) cfg = {64, 64, 16};
-  bool ok = false;
-  for (auto& c : hs::fp64_configs())
-    if (c.tm == cfg.tm && c.tn == cfg.tn && c.kc == cfg.kc) ok = true;
-  if (!ok) {
-    delete p;
-    return invalid("tile configuration (tile_m, tile_n, kc) not compiled into the library");
+  if (o.prec == HSUMMA_FP64) {
+    hs::TileCfg cfg{o.tile_m ? o.tile_m : 128, o.tile_n ? o.tile_n : 128, o.kc ? o.kc : 16};
+    if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) cfg = {64, 64, 16};
+    bool ok = false;
+    for (auto& c : hs::fp64_configs())
+      if (c.tm == cfg.tm && c.tn == cfg.tn && c.kc == cfg.kc) ok = true;
+    if (!ok) {
+      delete p;
+      return invalid("tile configuration (tile_m, tile_n, kc) not compiled into the library");
+    }
+    p->cfg = cfg;
+  } else {
+    p->fmt = o.prec == HSUMMA_SPLIT_BF16 ? 0 : 1;
+    if ((o.tile_m && o.tile_m != 64) || (o.tile_n && o.tile_n != 64) ||
+        (o.kc && o.kc != hs::kSplitChunk)) {
+      delete p;
+      return invalid("split forms use 64 x 64 macro-tiles with k-chunk 32");
+    }
+    p->cfg = {64, 64, hs::kSplitChunk};
+    if (!p->opts.min_slices) p->opts.min_slices = 3;
+    if (!p->opts.max_slices) p->opts.max_slices = hs::kSplitMaxSlices;
+    if (!p->opts.tau_bits) p->opts.tau_bits = 51;
+    const int smin = p->opts.min_slices, smax = p->opts.max_slices, sf = p->opts.slices;
+    if (smin < 1 || smax > hs::kSplitMaxSlices || smin > smax || sf < 0 ||
+        sf > hs::kSplitMaxSlices) {
+      delete p;
+      return invalid("slice counts must satisfy 1 <= min_slices <= max_slices <= 7, slices <= 7");
+    }
+    if (sf > smax) p->opts.max_slices = sf;
+    if (p->fmt == 1 && M > 8192) {
+      delete p;
+      return invalid("FP8 split form needs M <= 8192 (exact FP32 accumulation over a panel)");
+    }
+    if (m >= (1LL << 31) / 1 || n >= (1LL << 31)) {
+      delete p;
+      return invalid("matrix too large for the split form");
+    }
+    const int64_t Wp = (M + hs::kSplitChunk - 1) / hs::kSplitChunk * hs::kSplitChunk;
+    p->Wp = (int32_t)Wp;
+    const int64_t esz = p->fmt == 0 ? 2 : 1;
+    const int64_t nout = (k + M - 1) / M;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    p->off_digA = off; off = al(off + (size_t)(p->opts.max_slices * m * Wp * esz));
+    p->off_digB = off; off = al(off + (size_t)(p->opts.max_slices * n * Wp * esz));
+    p->off_eA = off; off = al(off + (size_t)m * 4);
+    p->off_fB = off; off = al(off + (size_t)n * 4);
+    p->off_stats = off; off = al(off + (size_t)std::max<int64_t>(1, nout) * 8);
+    p->off_slices = off; off = al(off + (size_t)std::max<int64_t>(1, nout) * 4);
+    p->ws_bytes = off;
   }
-  p->cfg = cfg;
 
   p->rlo = block_bounds(m, P);
   p->clo = block_bounds(n, Q);
@@ -346,7 +436,7 @@ void hsumma_plan_destroy(hsumma_plan_t p) {
 
 int hsumma_workspace_size(hsumma_plan_t p, size_t* bytes) {
   if (!p || !bytes) return invalid("null argument");
-  *bytes = 0;
+  *bytes = p->ws_bytes;
   return HSUMMA_OK;
 }
 
@@ -416,9 +506,9 @@ int hsumma_local_update(hsumma_plan_t p, int64_t step, const double* A, int64_t 
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
   if (step < 0 || step >= (int64_t)p->steps.size()) return invalid("step out of range");
-  (void)ws; (void)ws_bytes;
   const StepRec& st = p->steps[step];
-  return launch_range(p, A, lda, B, ldb, C, ldc, st.k0, st.k1, 0, (hipStream_t)stream);
+  return launch_range(p, A, lda, B, ldb, C, ldc, st.k0, st.k1, 0, st.outer, ws, ws_bytes,
+                      (hipStream_t)stream);
 }
 
 int hsumma_outer_update(hsumma_plan_t p, int64_t outer, const double* A, int64_t lda,
@@ -427,18 +517,17 @@ int hsumma_outer_update(hsumma_plan_t p, int64_t outer, const double* A, int64_t
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
   if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
-  (void)ws; (void)ws_bytes;
   return launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1], 0,
-                      (hipStream_t)stream);
+                      outer, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
                double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream) {
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
-  (void)ws_bytes;
   hipStream_t s = (hipStream_t)stream;
-  if (!p->opts.use_graph || s == nullptr) return run_direct(p, A, lda, B, ldb, C, ldc, s);
+  if (!p->opts.use_graph || s == nullptr)
+    return run_direct(p, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
 
   // Graph mode: capture the launch sequence once per (pointers, stream).
   hs::WorkItem* items = nullptr;
@@ -454,7 +543,7 @@ int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, i
       p->have_graph = false;
     }
     HS_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, s);
+    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (rc2) {
@@ -481,10 +570,47 @@ int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, i
 }
 
 int hsumma_panel_slices(hsumma_plan_t p, const void* ws, int32_t* counts, void* stream) {
-  (void)ws; (void)counts; (void)stream;
+  if (!p || !counts) return invalid("null argument");
+  if (p->fmt < 0) {
+    set_error("the FP64 path has no slices");
+    return HSUMMA_ERR_UNSUPPORTED;
+  }
+  if (!ws) return invalid("null workspace");
+  const int64_t nout = (int64_t)p->outer_lo.size() - 1;
+  hipStream_t s = (hipStream_t)stream;
+  HS_CHECK_HIP(hipMemcpyAsync(counts, (const uint8_t*)ws + p->off_slices, (size_t)nout * 4,
+                              hipMemcpyDeviceToHost, s));
+  HS_CHECK_HIP(hipStreamSynchronize(s));
+  return HSUMMA_OK;
+}
+
+int hsumma_split_layout(hsumma_plan_t p, size_t* off_digA, size_t* off_digB, size_t* off_eA,
+                        size_t* off_fB, int32_t* Wp, int32_t* planes) {
   if (!p) return invalid("null plan");
-  set_error("no split-form panel in this plan");
-  return HSUMMA_ERR_UNSUPPORTED;
+  if (p->fmt < 0) {
+    set_error("the FP64 path has no split workspace");
+    return HSUMMA_ERR_UNSUPPORTED;
+  }
+  if (off_digA) *off_digA = p->off_digA;
+  if (off_digB) *off_digB = p->off_digB;
+  if (off_eA) *off_eA = p->off_eA;
+  if (off_fB) *off_fB = p->off_fB;
+  if (Wp) *Wp = p->Wp;
+  if (planes) *planes = p->opts.max_slices;
+  return HSUMMA_OK;
+}
+
+int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k, float* d,
+                            void* stream) {
+  if (fmt != 0 && fmt != 1) return invalid("fmt must be 0 (BF16) or 1 (FP8-e4m3)");
+  if (!a || !b || !d) return invalid("null pointer");
+  if (k < 32 || k % 32) return invalid("k must be a positive multiple of 32");
+  hipError_t e = hs::launch_mfma_probe(fmt, a, b, k, d, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    set_error(std::string("probe launch: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
+  }
+  return HSUMMA_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,508 @@
+// Precision form of the local update: FP64 operands split into small-integer
+// digit planes (BF16 or FP8-e4m3), products of the planes on the matrix
+// cores with FP32 accumulation that is exact by construction, and FP64
+// recombination.  An error-free splitting in the spirit of Ozaki, Ogita,
+// Oishi and Rump (Numer. Algorithms 59, 2012); not part of the HSUMMA paper,
+// which only fixes the update C += A_panel x B_panel being computed.
+//
+// Digit rule, per outer panel (k-columns [k0, k0 + w)):
+//   e_i  = smallest integer with max_l |a_il| <= 2^e_i   (A row i; 0 if zero)
+//   f_j  = the same over B column j
+//   x    = a 2^-e in [-1, 1];  d_1 = rint(x 2^H), r_1 = x 2^H - d_1,
+//          d_l = rint(r_{l-1} 2^T), r_l = r_{l-1} 2^T - d_l   (round half even)
+//   BF16: H = 8, T = 9; FP8-e4m3: H = 4, T = 5; every |d| <= 2^H, exact in
+//   the narrow format.  BF16 planes hold d_l 2^(-T (l-1)) (a power-of-two
+//   scale, still exact) so that the product of planes l1 and l2 already
+//   carries its weight 2^(-T (l1 + l2 - 2)).
+//
+// Products: the digit pairs (l1, l2) with l1 + l2 <= s + 1 (1-based), s the
+// panel's slice count.  Pairs of one level L = l1 + l2 share an FP32
+// accumulator.  BF16: levels 2..5 are exact accumulators (at most 4 pairs
+// x 64 k x 2^16 <= 2^24), deeper levels (weight <= 2^-36) share one
+// accumulator whose FP32 rounding stays below 2^-60 of the leading term;
+// every 64 k the accumulators are added into an FP64 panel sum.  FP8: every
+// level is exact over the whole panel (7 pairs x 2^8 x w <= 2^24 for
+// w <= 9362) and is added, scaled by 2^(-T (L - 2)), at the end of the panel.
+// Finally C += 2^(e_i + f_j - 2H) x panel sum, in FP64.
+#include "internal.h"
+#include "split.h"
+
+namespace hs {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ inline int exponent_bound(double mx) {
+  if (!(mx > 0.0)) return 0;
+  int e;
+  const double f = frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+  return f == 0.5 ? e - 1 : e;
+}
+
+__device__ inline uint8_t e4m3_of_int(int d) {
+  // OCP e4m3fn encoding of an integer with |d| <= 16 (exact).
+  const int a = d < 0 ? -d : d;
+  uint8_t bits = 0;
+  if (a) {
+    const int E = 31 - __clz(a);          // 0..4
+    const int Mt = ((a << 3) >> E) - 8;   // 3-bit mantissa, exact for |d| <= 16
+    bits = (uint8_t)(((E + 7) << 3) | Mt);
+  }
+  return (uint8_t)(bits | (d < 0 ? 0x80 : 0));
+}
+
+template <int FMT>
+__device__ inline void split_value(double a, int e, int smax, uint16_t* out16, uint8_t* out8,
+                                   int64_t plane_stride, int64_t pos) {
+  constexpr int H = FMT == 0 ? 8 : 4;
+  constexpr int T = FMT == 0 ? 9 : 5;
+  double r = ldexp(a, -e);
+  int shift = H;
+  for (int l = 0; l < smax; ++l) {
+    const double y = ldexp(r, shift);
+    const double d = rint(y);
+    r = y - d;
+    shift = T;
+    if (FMT == 0) {
+      const float f = (float)ldexp(d, -T * l);  // d 2^(-T l): <= 9 significant bits
+      out16[l * plane_stride + pos] = (uint16_t)(__float_as_uint(f) >> 16);
+    } else {
+      out8[l * plane_stride + pos] = e4m3_of_int((int)d);
+    }
+  }
+}
+
+// ---- A rows: one wave per row ------------------------------------------------
+template <int FMT>
+__global__ __launch_bounds__(256) void split_rows_kernel(SplitArgs p) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wave;
+  if (i >= p.m) return;  // whole wave leaves; this kernel has no barrier
+  const double* row = p.A + (int64_t)i * p.lda + p.k0;
+  double mx = 0.0, sm = 0.0;
+  for (int kk = lane; kk < p.w; kk += 64) {
+    const double a = fabs(row[kk]);
+    mx = fmax(mx, a);
+    sm += a;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o));
+    sm += __shfl_xor(sm, o);
+  }
+  const int e = exponent_bound(mx);
+  if (lane == 0) {
+    p.eA[i] = e;
+    if (sm > 0.0) {
+      const float kap = (float)log2(mx * (double)p.w / sm);
+      atomicMax(&p.stats[0], __float_as_uint(fmaxf(kap, 0.0f)));
+    }
+  }
+  uint16_t* o16 = (uint16_t*)p.digA;
+  uint8_t* o8 = (uint8_t*)p.digA;
+  for (int kk = lane; kk < p.Wp; kk += 64) {
+    const double a = kk < p.w ? row[kk] : 0.0;
+    split_value<FMT>(a, e, p.smax, o16, o8, p.planeA, (int64_t)i * p.Wp + kk);
+  }
+}
+
+// ---- B columns: 64 columns per workgroup, digits written transposed ----------
+template <int FMT>
+__global__ __launch_bounds__(256) void split_cols_kernel(SplitArgs p) {
+  constexpr int PADE = 8;                    // row padding (elements)
+  constexpr int RS = 64 + PADE;              // LDS row stride (elements)
+  __shared__ double red_mx[4][64], red_sm[4][64];
+  __shared__ int sexp[64];
+  __shared__ uint16_t tile[kSplitMaxSlices * 64 * RS];
+
+  const int tid = threadIdx.x;
+  const int c = tid & 63, part = tid >> 6;
+  const int j0 = blockIdx.x * 64;
+  const int j = j0 + c;
+  const bool valid = j < p.n;
+  const double* col = p.B + (int64_t)p.k0 * p.ldb + j;
+
+  double mx = 0.0, sm = 0.0;
+  if (valid)
+    for (int r = part; r < p.w; r += 4) {
+      const double v = fabs(col[(int64_t)r * p.ldb]);
+      mx = fmax(mx, v);
+      sm += v;
+    }
+  red_mx[part][c] = mx;
+  red_sm[part][c] = sm;
+  __syncthreads();
+  if (part == 0) {
+    for (int q = 1; q < 4; ++q) {
+      mx = fmax(mx, red_mx[q][c]);
+      sm += red_sm[q][c];
+    }
+    const int f = exponent_bound(mx);
+    sexp[c] = f;
+    float kap = 0.0f;
+    if (valid) {
+      p.fB[j] = f;
+      if (sm > 0.0) kap = fmaxf((float)log2(mx * (double)p.w / sm), 0.0f);
+    }
+    for (int o = 32; o > 0; o >>= 1) kap = fmaxf(kap, __shfl_xor(kap, o));
+    if (c == 0) atomicMax(&p.stats[1], __float_as_uint(kap));
+  }
+  __syncthreads();
+  const int f = sexp[c];
+
+  for (int rb = 0; rb < p.Wp; rb += 64) {
+    for (int u = 0; u < 16; ++u) {
+      const int kl = part * 16 + u;
+      const int kk = rb + kl;
+      const double v = (valid && kk < p.w) ? col[(int64_t)kk * p.ldb] : 0.0;
+      constexpr int H = FMT == 0 ? 8 : 4;
+      constexpr int T = FMT == 0 ? 9 : 5;
+      double r = ldexp(v, -f);
+      int shift = H;
+      for (int l = 0; l < p.smax; ++l) {
+        const double y = ldexp(r, shift);
+        const double d = rint(y);
+        r = y - d;
+        shift = T;
+        uint16_t bits;
+        if (FMT == 0)
+          bits = (uint16_t)(__float_as_uint((float)ldexp(d, -T * l)) >> 16);
+        else
+          bits = e4m3_of_int((int)d);
+        tile[(l * 64 + c) * RS + kl] = bits;
+      }
+    }
+    __syncthreads();
+    // write out: 64 columns x 64 k per plane, 16 elements per thread
+    const int cc = tid >> 2, seg = tid & 3;
+    if (j0 + cc < p.n) {
+      for (int l = 0; l < p.smax; ++l) {
+        const uint16_t* src = tile + (l * 64 + cc) * RS + seg * 16;
+        const int64_t pos = (int64_t)(j0 + cc) * p.Wp + rb + seg * 16;
+        if (FMT == 0) {
+          uint4* dst = (uint4*)((uint16_t*)p.digB + l * p.planeB + pos);
+          const uint4* s4 = (const uint4*)src;
+          dst[0] = s4[0];
+          dst[1] = s4[1];
+        } else {
+          uint32_t w[4];
+          for (int q = 0; q < 4; ++q)
+            w[q] = (uint32_t)src[4 * q] | ((uint32_t)src[4 * q + 1] << 8) |
+                   ((uint32_t)src[4 * q + 2] << 16) | ((uint32_t)src[4 * q + 3] << 24);
+          *(uint4*)((uint8_t*)p.digB + l * p.planeB + pos) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---- slice products + recombination -----------------------------------------
+template <int FMT, int SMAX, int WM, int WN>
+struct SliceTile {
+  static constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
+  static constexpr int KC = 32;                          // k per MFMA step (one chunk)
+  static constexpr int ESZ = FMT == 0 ? 2 : 1;           // bytes per digit
+  static constexpr int ROWB = KC * ESZ + 16;             // LDS bytes per (plane, row)
+  static constexpr int UPR = KC * ESZ / 16;              // 16-byte units per (plane, row)
+  static constexpr int ABYTES = SMAX * TM * ROWB;
+  static constexpr int BBYTES = SMAX * TN * ROWB;
+  static constexpr int AUNITS = SMAX * TM * UPR;
+  static constexpr int BUNITS = SMAX * TN * UPR;
+  static constexpr int AU = (AUNITS + NT - 1) / NT;      // units per thread
+  static constexpr int BU = (BUNITS + NT - 1) / NT;
+  static constexpr int NACC = FMT == 0 ? (SMAX < 5 ? SMAX : 5) : SMAX;
+  static constexpr int REC = FMT == 0 ? 2 : 1 << 30;     // chunks between recombinations
+};
+
+template <int FMT, int SMAX, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64, 1)
+void slice_update_kernel(SliceArgs p) {
+  using T = SliceTile<FMT, SMAX, WM, WN>;
+  constexpr int H = FMT == 0 ? 8 : 4;
+  constexpr int TB = FMT == 0 ? 9 : 5;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[2 * (T::ABYTES + T::BBYTES)];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int l16 = lane & 15, lq = lane >> 4;
+
+  // slice count of this panel: fixed, or from the split's exponent statistics
+  int s = p.fixed_s;
+  if (s <= 0) {
+    const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
+    const float need = (float)p.tau_bits - (float)H + log2f(exp2f(ka) + exp2f(kb));
+    s = (int)ceilf(need / (float)TB) + 1;
+    s = max(p.smin, min(p.smax, s));
+  }
+  s = max(1, min(SMAX, s));
+  if (blockIdx.x == 0 && tid == 0 && p.slices_out) *p.slices_out = s;
+
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7;
+  const int slot0 = bid >> 3;
+  const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
+
+  for (int slot = slot0;; slot += slots) {
+    if (!p.persistent && slot != slot0) break;
+    if (slot >= p.per_xcd) break;
+    const int idx = xcd * p.per_xcd + slot;
+    if (idx >= p.nitems) break;
+    const WorkItem it = p.items[idx];
+
+    // global sources of this item's digit rows (rows past the item edge are
+    // clamped to its last row; their results are never stored)
+    const uint8_t* gA = (const uint8_t*)p.digA;
+    const uint8_t* gB = (const uint8_t*)p.digB;
+    const int64_t rowbytes = (int64_t)p.Wp * T::ESZ;
+
+    uint4 sa[T::AU], sb[T::BU];
+    auto load_chunk = [&](int ch) {
+#pragma unroll
+      for (int q = 0; q < T::AU; ++q) {
+        const int u = tid + q * T::NT;
+        const int plane = u / (T::TM * T::UPR);
+        const int rr = (u / T::UPR) % T::TM;
+        const int part = u % T::UPR;
+        if (u < T::AUNITS && plane < s) {
+          const int row = it.r0 + min(rr, it.h - 1);
+          sa[q] = *(const uint4*)(gA + plane * p.planeA * T::ESZ + row * rowbytes +
+                                  (int64_t)ch * T::KC * T::ESZ + part * 16);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < T::BU; ++q) {
+        const int u = tid + q * T::NT;
+        const int plane = u / (T::TN * T::UPR);
+        const int cc = (u / T::UPR) % T::TN;
+        const int part = u % T::UPR;
+        if (u < T::BUNITS && plane < s) {
+          const int col = it.c0 + min(cc, it.w - 1);
+          sb[q] = *(const uint4*)(gB + plane * p.planeB * T::ESZ + col * rowbytes +
+                                  (int64_t)ch * T::KC * T::ESZ + part * 16);
+        }
+      }
+    };
+    auto store_chunk = [&](uint8_t* base) {
+      uint8_t* As = base;
+      uint8_t* Bs = base + T::ABYTES;
+#pragma unroll
+      for (int q = 0; q < T::AU; ++q) {
+        const int u = tid + q * T::NT;
+        const int plane = u / (T::TM * T::UPR);
+        const int rr = (u / T::UPR) % T::TM;
+        const int part = u % T::UPR;
+        if (u < T::AUNITS && plane < s)
+          *(uint4*)(As + (plane * T::TM + rr) * T::ROWB + part * 16) = sa[q];
+      }
+#pragma unroll
+      for (int q = 0; q < T::BU; ++q) {
+        const int u = tid + q * T::NT;
+        const int plane = u / (T::TN * T::UPR);
+        const int cc = (u / T::UPR) % T::TN;
+        const int part = u % T::UPR;
+        if (u < T::BUNITS && plane < s)
+          *(uint4*)(Bs + (plane * T::TN + cc) * T::ROWB + part * 16) = sb[q];
+      }
+    };
+
+    f4 acc[T::NACC][2][2];
+    double cp[2][2][4];
+#pragma unroll
+    for (int a = 0; a < T::NACC; ++a)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[a][x][y] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cp[x][y][v] = 0.0;
+
+    auto recombine = [&]() {
+#pragma unroll
+      for (int a = T::NACC - 1; a >= 0; --a) {   // smallest weight first
+        const double wgt = FMT == 0 ? 1.0 : ldexp(1.0, -TB * a);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cp[x][y][v] = fma((double)acc[a][x][y][v], wgt, cp[x][y][v]);
+            acc[a][x][y] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    };
+
+    const int nch = p.nchunks;
+    load_chunk(0);
+    store_chunk(smem);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nch) load_chunk(ch + 1);
+      const uint8_t* As = smem + buf * (T::ABYTES + T::BBYTES);
+      const uint8_t* Bs = As + T::ABYTES;
+      if (FMT == 0) {
+        bf8v bfr[SMAX][2];
+#pragma unroll
+        for (int l2 = 0; l2 < SMAX; ++l2)
+          if (l2 < s)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              bfr[l2][y] = *(const bf8v*)(Bs + (l2 * T::TN + wn * 32 + y * 16 + l16) * T::ROWB + lq * 16);
+#pragma unroll
+        for (int l1 = 0; l1 < SMAX; ++l1) {
+          if (l1 < s) {
+            bf8v afr[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+              afr[x] = *(const bf8v*)(As + (l1 * T::TM + wm * 32 + x * 16 + l16) * T::ROWB + lq * 16);
+#pragma unroll
+            for (int l2 = 0; l2 < SMAX; ++l2) {
+              if (l1 + l2 < s) {
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int a = (l1 + l2) < T::NACC - 1 ? (l1 + l2) : T::NACC - 1;
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                  for (int y = 0; y < 2; ++y)
+                    acc[a][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[x], bfr[l2][y], acc[a][x][y], 0, 0, 0);
+              }
+            }
+          }
+        }
+      } else {
+        long bfr[SMAX][2];
+#pragma unroll
+        for (int l2 = 0; l2 < SMAX; ++l2)
+          if (l2 < s)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              bfr[l2][y] = *(const long*)(Bs + (l2 * T::TN + wn * 32 + y * 16 + l16) * T::ROWB + lq * 8);
+#pragma unroll
+        for (int l1 = 0; l1 < SMAX; ++l1) {
+          if (l1 < s) {
+            long afr[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+              afr[x] = *(const long*)(As + (l1 * T::TM + wm * 32 + x * 16 + l16) * T::ROWB + lq * 8);
+#pragma unroll
+            for (int l2 = 0; l2 < SMAX; ++l2) {
+              if (l1 + l2 < s) {
+                const int a = l1 + l2;
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                  for (int y = 0; y < 2; ++y)
+                    acc[a][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(afr[x], bfr[l2][y], acc[a][x][y], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+      if ((ch + 1) % T::REC == 0 || ch + 1 == nch) recombine();
+      if (ch + 1 < nch) store_chunk(smem + (buf ^ 1) * (T::ABYTES + T::BBYTES));
+      __syncthreads();
+    }
+
+    // C += 2^(e_i + f_j - 2H) x panel sum
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int col = wn * 32 + y * 16 + l16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = wm * 32 + x * 16 + 4 * lq + v;
+          if (row < it.h && col < it.w) {
+            const int gr = it.r0 + row, gc = it.c0 + col;
+            const double add = ldexp(cp[x][y][v], p.eA[gr] + p.fB[gc] - 2 * H);
+            double* cptr = p.C + (int64_t)gr * p.ldc + gc;
+            *cptr = p.zero_init ? add : *cptr + add;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---- self-test of the matrix-core accumulation -------------------------------
+// D (16 x 16, FP32) = A (16 x k digits, row-major) x B (k x 16 digits,
+// row-major) by chained 16x16x32 MFMAs with FP32 accumulation, exactly as the
+// slice-product kernel accumulates one level.  One wave.
+template <int FMT>
+__global__ __launch_bounds__(64) void mfma_probe_kernel(const void* a, const void* b, int k,
+                                                         float* out) {
+  const int l = threadIdx.x, l16 = l & 15, lq = l >> 4;
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < k; kc += 32) {
+    if (FMT == 0) {
+      const uint16_t* A = (const uint16_t*)a;
+      const uint16_t* B = (const uint16_t*)b;
+      bf8v av, bv;
+      for (int e = 0; e < 8; ++e) {
+        const int kk = kc + lq * 8 + e;
+        av[e] = __builtin_bit_cast(__bf16, A[l16 * k + kk]);
+        bv[e] = __builtin_bit_cast(__bf16, B[kk * 16 + l16]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    } else {
+      const uint8_t* A = (const uint8_t*)a;
+      const uint8_t* B = (const uint8_t*)b;
+      long av = 0, bv = 0;
+      for (int e = 0; e < 8; ++e) {
+        const int kk = kc + lq * 8 + e;
+        av |= (long)A[l16 * k + kk] << (8 * e);
+        bv |= (long)B[kk * 16 + l16] << (8 * e);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+    }
+  }
+  for (int v = 0; v < 4; ++v) out[(4 * lq + v) * 16 + l16] = acc[v];
+}
+
+hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float* out,
+                             hipStream_t s) {
+  if (fmt == 0)
+    hipLaunchKernelGGL(mfma_probe_kernel<0>, dim3(1), dim3(64), 0, s, a, b, k, out);
+  else
+    hipLaunchKernelGGL(mfma_probe_kernel<1>, dim3(1), dim3(64), 0, s, a, b, k, out);
+  return hipGetLastError();
+}
+
+// ---- launchers ----------------------------------------------------------------
+hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
+  const int gr = (a.m + 3) / 4, gc = (a.n + 63) / 64;
+  if (a.fmt == 0) {
+    hipLaunchKernelGGL(split_rows_kernel<0>, dim3(gr), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(split_cols_kernel<0>, dim3(gc), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(split_rows_kernel<1>, dim3(gr), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(split_cols_kernel<1>, dim3(gc), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* ptr, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ptr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s) {
+  if (fmt == 0)
+    hipLaunchKernelGGL((slice_update_kernel<0, kSplitMaxSlices, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((slice_update_kernel<1, kSplitMaxSlices, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace hs

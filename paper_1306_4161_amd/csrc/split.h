@@ -1,0 +1,41 @@
+// Internal interface of the precision-form kernels (digit split + slice products).
+#pragma once
+
+#include "internal.h"
+
+namespace hs {
+
+constexpr int kSplitMaxSlices = 7;   // digit planes written per operand
+constexpr int kSplitChunk = 32;      // k per slice-product step; panel width padded to this
+
+struct SplitArgs {
+  const double* A; int64_t lda;      // panel = A(:, k0:k0+w)
+  const double* B; int64_t ldb;      // panel = B(k0:k0+w, :)
+  int32_t m, n, k0, w, Wp;           // Wp: padded panel width (multiple of kSplitChunk)
+  int32_t fmt;                       // 0: BF16 digits, 1: FP8-e4m3 digits
+  int32_t smax;                      // planes to write
+  void* digA; int64_t planeA;        // planes of m x Wp digits (elements per plane)
+  void* digB; int64_t planeB;        // planes of n x Wp digits (B transposed)
+  int32_t* eA; int32_t* fB;          // per-row / per-column exponents
+  uint32_t* stats;                   // [0]: max log2 kappa over A rows, [1]: over B cols
+};
+
+struct SliceArgs {
+  const void* digA; int64_t planeA;
+  const void* digB; int64_t planeB;
+  const int32_t* eA; const int32_t* fB;
+  const uint32_t* stats; int32_t* slices_out;
+  double* C; int64_t ldc;
+  const WorkItem* items; int32_t nitems; int32_t per_xcd;
+  int32_t Wp, nchunks;
+  int32_t fixed_s, smin, smax, tau_bits;
+  int32_t zero_init, persistent;
+};
+
+hipError_t launch_split(const SplitArgs& a, hipStream_t s);
+hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float* out,
+                             hipStream_t s);
+
+}  // namespace hs

@@ -21,6 +21,7 @@ EXPORTED = [
     "hsumma_num_steps", "hsumma_num_outer_steps", "hsumma_groups", "hsumma_tile_shape",
     "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
+    "hsumma_split_layout", "hsumma_mfma_exact_probe",
 ]
 
 
@@ -32,7 +33,8 @@ class Opts(ctypes.Structure):
         ("slices", ctypes.c_int32), ("min_slices", ctypes.c_int32), ("max_slices", ctypes.c_int32),
         ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32), ("kc", ctypes.c_int32),
         ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("tau_bits", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -73,6 +75,9 @@ def lib():
         L.hsumma_outer_update.argtypes = upd
         L.hsumma_run.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
         L.hsumma_panel_slices.argtypes = [vp, vp, P(i32), vp]
+        sz = ctypes.c_size_t
+        L.hsumma_split_layout.argtypes = [vp, P(sz), P(sz), P(sz), P(sz), P(i32), P(i32)]
+        L.hsumma_mfma_exact_probe.argtypes = [i32, vp, vp, i32, vp, vp]
         L.hsumma_last_error.restype = ctypes.c_char_p
         L.hsumma_last_error.argtypes = []
         L.hsumma_version.restype = ctypes.c_char_p
@@ -115,14 +120,14 @@ class Plan:
 
     def __init__(self, n, P, Q, G, b, M=None, *, m=0, k=0, dist=DIST_BLOCK, nb=0,
                  prec=FP64, slices=0, min_slices=0, max_slices=0, tile_m=0, tile_n=0,
-                 kc=0, persistent=0, use_graph=0):
+                 kc=0, persistent=0, use_graph=0, tau_bits=0):
         L = lib()
         o = Opts()
         L.hsumma_opts_default(ctypes.byref(o))
         o.m, o.k, o.dist, o.nb, o.prec = m, k, dist, nb, prec
         o.slices, o.min_slices, o.max_slices = slices, min_slices, max_slices
         o.tile_m, o.tile_n, o.kc = tile_m, tile_n, kc
-        o.persistent, o.use_graph = persistent, use_graph
+        o.persistent, o.use_graph, o.tau_bits = persistent, use_graph, tau_bits
         h = ctypes.c_void_p()
         _check(L.hsumma_plan(ctypes.byref(h), n, P, Q, G, b, M if M is not None else b,
                              ctypes.byref(o)))
@@ -130,6 +135,7 @@ class Plan:
         self.n, self.m, self.k = n, (m or n), (k or n)
         self.P, self.Q, self.G, self.b = P, Q, G, b
         self.M = M if M is not None else b
+        self.prec = prec
 
     def close(self):
         if getattr(self, "_h", None):
@@ -225,6 +231,26 @@ class Plan:
         _check(lib().hsumma_panel_slices(self._h, ctypes.c_void_p(ws.data_ptr()), out,
                                          _stream(stream)))
         return list(out)
+
+
+    def split_layout(self):
+        v = [ctypes.c_size_t() for _ in range(4)]
+        w, np_ = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().hsumma_split_layout(self._h, *[ctypes.byref(x) for x in v],
+                                         ctypes.byref(w), ctypes.byref(np_)))
+        return dict(off_digA=v[0].value, off_digB=v[1].value, off_eA=v[2].value,
+                    off_fB=v[3].value, Wp=w.value, planes=np_.value)
+
+
+def mfma_exact_probe(fmt, a_digits, b_digits, stream=None):
+    """16 x 16 FP32 product of digit matrices on the matrix cores (see header)."""
+    import torch
+    k = a_digits.shape[1]
+    d = torch.empty((16, 16), dtype=torch.float32, device="cuda")
+    _check(lib().hsumma_mfma_exact_probe(fmt, ctypes.c_void_p(a_digits.data_ptr()),
+                                         ctypes.c_void_p(b_digits.data_ptr()), k,
+                                         ctypes.c_void_p(d.data_ptr()), _stream(stream)))
+    return d
 
 
 def version():

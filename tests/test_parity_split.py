@@ -1,0 +1,212 @@
+"""GPU parity of the precision form (BF16 / FP8-e4m3 digit split).
+
+Pins, in order of strength:
+  * the matrix cores accumulate integer digit products exactly while the
+    partial sums stay within 2^24 (hsumma_mfma_exact_probe vs Python ints);
+  * the digit planes and exponents the GPU writes equal the oracle's split
+    (oracle/split_ref.py) bit for bit;
+  * integer-valued operands that are one digit wide give the exact product;
+  * every entry is within FP64 accumulation error of the oracle's exact
+    value of the truncated split product (split_ref.truncated_entries);
+  * the accuracy gate: max |c_hat - c| / (|A||B|)_ij <= 1e-14 for BF16 with
+    the per-panel slice choice (c = Dot2 oracle), also reported for the plain
+    relative error.  FP8 (at most 34 bits with 7 slices) is reported, not gated.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core, split_ref
+from paper_1306_4161_amd import hsumma as hs
+from paper_1306_4161_amd import inputs
+
+from gpu_helpers import check_freivalds, dev, host
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-14
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(plan, A, B):
+    import torch
+    C = torch.empty((plan.m, plan.n), dtype=torch.float64, device="cuda")
+    ws = plan.workspace()
+    plan.run(dev(A) if isinstance(A, np.ndarray) else A,
+             dev(B) if isinstance(B, np.ndarray) else B, C, ws=ws)
+    return host(C), ws
+
+
+def _bf16_bits(x):
+    import torch
+    t = torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().astype(np.uint16)
+
+
+def _e4m3_bits(x):
+    import torch
+    t = torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.float8_e4m3fn)
+    return t.view(torch.uint8).numpy()
+
+
+# ------------------------------------------------------------- exactness --
+
+@pytest.mark.parametrize("fmt,lim,k", [(0, 256, 256), (0, 256, 64), (1, 16, 2048), (1, 16, 32)])
+def test_mfma_accumulation_exact_to_2_24(fmt, lim, k):
+    import torch
+    _say("case probe fmt=%d k=%d" % (fmt, k))
+    r = np.random.default_rng(k + fmt)
+    for trial in range(3):
+        if trial == 0:   # every partial sum as large as allowed
+            a = np.full((16, k), lim); b = np.full((k, 16), lim)
+            a[1::2] = -lim
+        else:
+            a = r.integers(-lim, lim + 1, (16, k)); b = r.integers(-lim, lim + 1, (k, 16))
+        bits = _bf16_bits if fmt == 0 else _e4m3_bits
+        da = torch.from_numpy(np.ascontiguousarray(bits(a))).cuda()
+        db = torch.from_numpy(np.ascontiguousarray(bits(b))).cuda()
+        d = hs.mfma_exact_probe(fmt, da, db)
+        exact = a.astype(object) @ b.astype(object)
+        got = host(d).astype(np.float64)
+        assert np.array_equal(got, exact.astype(np.float64)), (fmt, k, trial)
+        assert np.abs(exact).max() <= 2 ** 24
+
+
+# ------------------------------------------------------------ split stage --
+
+@pytest.mark.parametrize("prec,fmt", [(hs.SPLIT_BF16, "bf16"), (hs.SPLIT_FP8, "e4m3")])
+def test_digit_planes_match_oracle_bitwise(prec, fmt):
+    import torch
+    _say("case split planes %s" % fmt)
+    m, k, n, M = 96, 100, 80, 100
+    A = inputs.exponent_spread(m, k, 3, sigma=2.0)
+    B = inputs.exponent_spread(k, n, 4, sigma=2.0)
+    p = hs.Plan(n, 2, 2, 1, 100, M, m=m, k=k, prec=prec)
+    C, ws = _run(p, A, B)
+    lay = p.split_layout()
+    Wp, planes = lay["Wp"], lay["planes"]
+    raw = ws.cpu().numpy()
+    esz = 2 if fmt == "bf16" else 1
+    dt = np.uint16 if esz == 2 else np.uint8
+    digA = raw[lay["off_digA"]: lay["off_digA"] + planes * m * Wp * esz].view(dt).reshape(planes, m, Wp)
+    digB = raw[lay["off_digB"]: lay["off_digB"] + planes * n * Wp * esz].view(dt).reshape(planes, n, Wp)
+    eA = raw[lay["off_eA"]: lay["off_eA"] + 4 * m].view(np.int32)
+    fB = raw[lay["off_fB"]: lay["off_fB"] + 4 * n].view(np.int32)
+    e_ref = split_ref.exponents(A, axis=1)
+    f_ref = split_ref.exponents(B, axis=0)
+    assert np.array_equal(eA, e_ref) and np.array_equal(fB, f_ref)
+    DA = split_ref.digits(A, e_ref, planes, fmt, axis=1)       # (s, m, k)
+    DB = split_ref.digits(B, f_ref, planes, fmt, axis=0)       # (s, k, n)
+    t = split_ref.FORMATS[fmt][1]
+    for l in range(planes):
+        if fmt == "bf16":
+            wa = _bf16_bits(np.ldexp(DA[l], -t * l))
+            wb = _bf16_bits(np.ldexp(DB[l].T, -t * l))
+        else:
+            # a zero digit may come out as +0 or -0 (0x80); both are the value 0
+            wa = _e4m3_bits(DA[l]); wa[wa == 0x80] = 0
+            wb = _e4m3_bits(DB[l].T); wb[wb == 0x80] = 0
+        assert np.array_equal(digA[l, :, :k], wa), l
+        assert np.array_equal(digB[l, :, :k], wb), l
+        assert not digA[l, :, k:].any() and not digB[l, :, k:].any()
+
+
+# -------------------------------------------------------- exact products --
+
+@pytest.mark.parametrize("prec,r", [(hs.SPLIT_BF16, 8), (hs.SPLIT_FP8, 4)])
+def test_integer_operands_one_digit_exact(prec, r):
+    _say("case integer one-digit prec=%d" % prec)
+    n = 320
+    A = inputs.integer_valued(n, n, 71, r)
+    B = inputs.integer_valued(n, n, 72, r)
+    for slices in (1, 3, 0):
+        p = hs.Plan(n, 2, 2, 4, 64, 128, prec=prec, slices=slices, min_slices=1)
+        C, _ = _run(p, A, B)
+        assert np.array_equal(C, core.gemm(A, B)), slices
+
+
+def test_identity_exact_for_six_digits():
+    # entries in +-[1/2, 1): six BF16 digits (8 + 5 x 9 = 53 bits) hold every
+    # bit, and B = I has one digit, so the product is exact
+    n = 256
+    r = np.random.default_rng(81)
+    A = r.uniform(0.5, 1.0, (n, n)) * r.choice([-1.0, 1.0], (n, n))
+    p = hs.Plan(n, 2, 2, 1, 128, 128, prec=hs.SPLIT_BF16, slices=6)
+    C, _ = _run(p, A, np.eye(n))
+    assert np.array_equal(C, A)
+
+
+# ---------------------------------------------- truncated product parity --
+
+@pytest.mark.parametrize("prec,fmt,s", [(hs.SPLIT_BF16, "bf16", 4), (hs.SPLIT_BF16, "bf16", 6),
+                                        (hs.SPLIT_FP8, "e4m3", 5)])
+def test_equals_truncated_split_product(prec, fmt, s):
+    _say("case truncated %s s=%d" % (fmt, s))
+    m, k, n, M = 130, 300, 110, 128
+    A = inputs.exponent_spread(m, k, 91, sigma=2.0)
+    B = inputs.exponent_spread(k, n, 92, sigma=2.0)
+    p = hs.Plan(n, 2, 2, 2, 64, M, m=m, k=k, prec=prec, slices=s, min_slices=1)
+    C, _ = _run(p, A, B)
+    rows, cols = np.meshgrid(np.arange(0, m, 3), np.arange(0, n, 4), indexing="ij")
+    rows, cols = rows.ravel(), cols.ravel()
+    T = split_ref.truncated_entries(A, B, M, s, fmt, rows, cols)
+    S = (np.abs(A) @ np.abs(B))[rows, cols]
+    # FP64 additions: one per level per 32..64 k plus one per panel
+    nadd = 8 * (k // 32 + 2) + 4 * (k // M + 1)
+    tol = nadd * core.U * (S + np.abs(T))
+    assert np.all(np.abs(C[rows, cols] - T) <= tol)
+
+
+# ---------------------------------------------------------- accuracy gate --
+
+@pytest.mark.parametrize("dist", ["uniform", "spread2"])
+def test_bf16_auto_slices_meet_gate(dist):
+    _say("case gate %s" % dist)
+    n = 1024
+    if dist == "uniform":
+        A = inputs.uniform(n, n, 101); B = inputs.uniform(n, n, 102)
+    else:
+        A = inputs.exponent_spread(n, n, 101, 2.0); B = inputs.exponent_spread(n, n, 102, 2.0)
+    p = hs.Plan(n, 4, 4, 4, 256, 256, prec=hs.SPLIT_BF16)
+    C, ws = _run(p, A, B)
+    rows, cols = inputs.sample_entries(n, n, 4096, inputs.SEED_SAMPLE)
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / s
+    _say("  slices per panel %r  max scaled err %.3g  max pure %.3g" % (
+        p.panel_slices(ws), err.max(), np.max(np.abs(C[rows, cols] - c) / np.abs(c))))
+    assert err.max() <= GATE
+    check_freivalds(A, B, C, seeds=(1,))
+
+
+def test_fp8_reports_error_within_truncation_bound():
+    n = 512
+    A = inputs.uniform(n, n, 111)
+    B = inputs.uniform(n, n, 112)
+    p = hs.Plan(n, 2, 2, 1, 256, 256, prec=hs.SPLIT_FP8, slices=7)
+    C, _ = _run(p, A, B)
+    rows, cols = inputs.sample_entries(n, n, 1024, 5)
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / s
+    # 7 e4m3 digits keep 4 + 5*6 = 34 bits of each operand
+    assert err.max() <= 64 * 2.0 ** -34
+    _say("  fp8 s=7 max scaled err %.3g" % err.max())
+
+
+def test_c2_shape_bf16_sampled():
+    _say("case c2 split-bf16 n=16384")
+    n = 16384
+    A = inputs.uniform(n, n, inputs.SEED_A)
+    B = inputs.uniform(n, n, inputs.SEED_B)
+    p = hs.Plan(n, 16, 16, 16, 256, 256, prec=hs.SPLIT_BF16)
+    C, ws = _run(p, A, B)
+    edges = [i * n // 16 for i in range(16)]
+    rows, cols = inputs.sample_entries(n, n, 2048, inputs.SEED_SAMPLE, edges, edges, per_edge=4)
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / s
+    _say("  slices %r max scaled err %.3g" % (sorted(set(p.panel_slices(ws))), err.max()))
+    assert err.max() <= GATE
