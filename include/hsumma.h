@@ -85,7 +85,9 @@ typedef struct {
   int32_t use_graph;  /* 1: hsumma_run replays a captured HIP graph             */
   int32_t tau_bits;   /* split forms, per-panel slice choice: target bits of    */
                       /* accuracy relative to (|A||B|)_ij; 0 => 51              */
-  int32_t reserved[5];
+  int32_t staged;     /* FP64 path: 1 = always the register-staged kernel,      */
+                      /* 0 = direct-to-LDS loads where alignment allows         */
+  int32_t reserved[4];
 } hsumma_opts;
 
 /* Fill *o with defaults (all zero: square, block, FP64, default tiles). */
@@ -157,10 +159,11 @@ int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, voi
 
 /*
  * Layout of the split forms' workspace after a call: byte offsets of the A
- * digit planes (planes x m x Wp digits, row-major, 2 B per BF16 digit or 1 B
- * per FP8-e4m3 digit), the B digit planes (planes x n x Wp, B transposed:
- * row j holds column j of the panel), the int32 row exponents of A and
- * column exponents of B.  They hold the most recently split panel.  Lets a
+ * digit planes (planes x m x Wp digits, 2 B per BF16 digit or 1 B per
+ * FP8-e4m3 digit, stored k16-block-major: digit (plane, row, k) at
+ * plane*m*Wp + (k/16)*m*16 + row*16 + k%16), the B digit planes (the same
+ * with n columns: B transposed), the int32 row exponents of A and column
+ * exponents of B.  They hold the most recently split panel.  Lets a
  * caller inspect the split; HSUMMA_ERR_UNSUPPORTED for the FP64 path.
  */
 int hsumma_split_layout(hsumma_plan_t plan, size_t* off_digA, size_t* off_digB,
@@ -176,6 +179,31 @@ int hsumma_split_layout(hsumma_plan_t plan, size_t* off_digA, size_t* off_digB,
  */
 int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k, float* d,
                             void* stream);
+
+/*
+ * Learned cost model (the tuner's learned form): a 3-layer FP32 MLP
+ *   Z = relu(relu(X W1 + b1) W2 + b2) W3 + b3
+ * with X: N x F features per problem shape, H hidden units, and one output
+ * per candidate kernel configuration (its predicted log run time).  All
+ * pointers are device memory, row-major; `params` packs W1 (F x H), b1 (H),
+ * W2 (H x H), b2 (H), W3 (H x K), b3 (K); `grads` has the same layout.
+ * `work` holds hsumma_mlp_work_floats(N, H, K) floats.  Asynchronous on
+ * `stream`.  Not part of the paper: it predicts the fastest configuration
+ * so that exhaustive tuning can be skipped.
+ */
+int64_t hsumma_mlp_param_count(int32_t F, int32_t H, int32_t K);   /* -1 on bad dims */
+int64_t hsumma_mlp_work_floats(int32_t N, int32_t H, int32_t K);
+/* Z (N x K) = network(X) */
+int hsumma_mlp_forward(int32_t N, int32_t F, int32_t H, int32_t K, const float* X,
+                       const float* params, float* Z, float* work, void* stream);
+/* Forward, masked mean squared error against T (mask 1 = timed candidate),
+ * and gradients of that loss w.r.t. every parameter; *loss on device. */
+int hsumma_mlp_grad(int32_t N, int32_t F, int32_t H, int32_t K, const float* X, const float* T,
+                    const float* mask, const float* params, float* grads, float* Z, float* loss,
+                    float* work, void* stream);
+/* One Adam step (bias-corrected, step counts from 1) over n parameters. */
+int hsumma_mlp_adam(int64_t n, float* params, const float* grads, float* m, float* v, float lr,
+                    float beta1, float beta2, float eps, int32_t step, void* stream);
 
 /* Message for the last failure on this thread ("" if none). */
 const char* hsumma_last_error(void);

@@ -57,6 +57,7 @@ struct hsumma_plan_s {
   std::vector<int64_t> outer_lo;              // k start of each outer step (+ end)
   std::vector<hs::WorkItem> items;
   int32_t per_xcd = 0;
+  bool items_even = false;     // every work item starts at an even column, has even width
   // precision form: workspace layout (byte offsets) and panel geometry
   int32_t fmt = -1;            // -1: FP64 path; 0: BF16 digits; 1: FP8-e4m3 digits
   int32_t Wp = 0;              // padded panel width
@@ -164,6 +165,9 @@ void build_items(hsumma_plan_s& p) {
         }
   const int64_t nit = (int64_t)p.items.size();
   p.per_xcd = (int32_t)((nit + 7) / 8);
+  p.items_even = true;
+  for (auto& it : p.items)
+    if ((it.c0 | it.w) & 1) p.items_even = false;
   if (p.opts.persistent) {
     // Longest-processing-time order inside each XCD's list, so that the
     // static round-robin of the persistent workgroups stays balanced when
@@ -240,7 +244,12 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
     a.items = items; a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;
     a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
     a.persistent = p->opts.persistent;
-    hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream);
+    // direct-to-LDS loads move 16-byte units: every k bound, leading
+    // dimension and column offset must be even and the operands aligned
+    const bool dma = !p->opts.staged && hs::fp64_has_dma(p->cfg) && p->items_even &&
+                     !((k0 | k1 | p->b | lda | ldb) & 1) &&
+                     !(((uintptr_t)A | (uintptr_t)B) & 15);
+    hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream, dma);
     if (e != hipSuccess) {
       set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));
       return HSUMMA_ERR_DEVICE;
@@ -265,7 +274,8 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   hs::SplitArgs sa;
   sa.A = A; sa.lda = lda; sa.B = B; sa.ldb = ldb;
   sa.m = (int32_t)p->m; sa.n = (int32_t)p->n; sa.k0 = (int32_t)k0; sa.w = (int32_t)(k1 - k0);
-  sa.Wp = (int32_t)(((k1 - k0) + hs::kSplitChunk - 1) / hs::kSplitChunk * hs::kSplitChunk);
+  const int64_t pad = p->fmt == 0 ? 64 : hs::kSplitChunk;
+  sa.Wp = (int32_t)(((k1 - k0) + pad - 1) / pad * pad);
   sa.fmt = p->fmt;
   sa.smax = p->opts.max_slices;
   sa.digA = w8 + p->off_digA; sa.planeA = (int64_t)p->m * sa.Wp;
@@ -278,7 +288,8 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
     return HSUMMA_ERR_DEVICE;
   }
   hs::SliceArgs la;
-  la.digA = sa.digA; la.planeA = sa.planeA; la.digB = sa.digB; la.planeB = sa.planeB;
+  la.digA = sa.digA; la.planeA = sa.planeA; la.rowsA = sa.m;
+  la.digB = sa.digB; la.planeB = sa.planeB; la.rowsB = sa.n;
   la.eA = sa.eA; la.fB = sa.fB; la.stats = stats;
   la.slices_out = (int32_t*)(w8 + p->off_slices) + slot;
   la.C = C; la.ldc = ldc;
@@ -366,12 +377,14 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     p->cfg = cfg;
   } else {
     p->fmt = o.prec == HSUMMA_SPLIT_BF16 ? 0 : 1;
-    if ((o.tile_m && o.tile_m != 64) || (o.tile_n && o.tile_n != 64) ||
-        (o.kc && o.kc != hs::kSplitChunk)) {
+    // BF16: 64 x 128 macro-tiles streamed in 16-k steps; FP8: 64 x 64, 32-k steps
+    const hs::TileCfg scfg = p->fmt == 0 ? hs::TileCfg{64, 128, 16} : hs::TileCfg{64, 64, 32};
+    if ((o.tile_m && o.tile_m != scfg.tm) || (o.tile_n && o.tile_n != scfg.tn) ||
+        (o.kc && o.kc != scfg.kc)) {
       delete p;
-      return invalid("split forms use 64 x 64 macro-tiles with k-chunk 32");
+      return invalid("split forms use fixed macro-tiles (BF16 64 x 128 x 16, FP8 64 x 64 x 32)");
     }
-    p->cfg = {64, 64, hs::kSplitChunk};
+    p->cfg = scfg;
     if (!p->opts.min_slices) p->opts.min_slices = 3;
     if (!p->opts.max_slices) p->opts.max_slices = hs::kSplitMaxSlices;
     if (!p->opts.tau_bits) p->opts.tau_bits = 51;
@@ -390,7 +403,8 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
       delete p;
       return invalid("matrix too large for the split form");
     }
-    const int64_t Wp = (M + hs::kSplitChunk - 1) / hs::kSplitChunk * hs::kSplitChunk;
+    const int64_t pad = p->fmt == 0 ? 64 : hs::kSplitChunk;   // BF16 steps in groups of 64 k
+    const int64_t Wp = (M + pad - 1) / pad * pad;
     p->Wp = (int32_t)Wp;
     const int64_t esz = p->fmt == 0 ? 2 : 1;
     const int64_t nout = (k + M - 1) / M;

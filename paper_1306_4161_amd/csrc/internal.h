@@ -35,7 +35,11 @@ struct UpdateArgs {
 // Kernel configurations (macro-tile and k-chunk) compiled into the library.
 struct TileCfg { int tm, tn, kc; };
 const std::vector<TileCfg>& fp64_configs();
-hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s);
+// dma: use the direct-to-LDS kernel of this configuration if there is one
+// (the caller guarantees 16-byte granularity of every k-range and column run)
+hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s,
+                       bool dma);
+bool fp64_has_dma(const TileCfg& cfg);
 int fp64_occupancy(const TileCfg& cfg);  // workgroups per CU the config is built for
 
 // Split (precision) path.

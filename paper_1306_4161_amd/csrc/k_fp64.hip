@@ -201,6 +201,187 @@ void fp64_update_kernel(UpdateArgs p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Direct-to-LDS variant (gfx950 global_load_lds_dwordx4): the chunk loads go
+// from global memory straight into an NS-stage LDS ring, with no staging
+// registers, so several chunks are in flight per workgroup.  Each
+// wave-instruction writes 64 consecutive 16-byte LDS units; which global
+// 16 bytes each lane fetches is free, so the ring holds swizzled images:
+//   A stage: As[row][u'] (row = 128 B = 8 units of 2 doubles),
+//            u' = u ^ ((row / 2) % 8)     -> fragment reads conflict-free
+//   B stage: Bs[k][u'] (row = TN doubles), u' = u ^ (8 (k % 2))
+// Lanes whose source is outside the item (ragged rows/cols) read a zero
+// page instead.  Used when every 16-byte unit is either wholly inside or
+// wholly outside the k-range (even k bounds, even leading dimensions, even
+// column offsets, 16-byte aligned operands); otherwise the staged kernel
+// above runs.
+__device__ __attribute__((aligned(16))) double g_zero_page[2] = {0.0, 0.0};
+
+template <int TM, int TN, int NS, int WM, int WN, int OCC>
+__global__ __launch_bounds__(WM * WN * 64, OCC)
+void fp64_dma_kernel(UpdateArgs p) {
+  constexpr int KC = 16;
+  constexpr int NT = WM * WN * 64, NW = WM * WN;
+  constexpr int WTM = TM / WM, WTN = TN / WN, FM = WTM / 16, FN = WTN / 16;
+  constexpr int ABYTES = TM * KC * 8, BBYTES = KC * TN * 8, SBYTES = ABYTES + BBYTES;
+  constexpr int AINS = ABYTES / 1024 / NW;   // A wave-instructions per wave per chunk
+  constexpr int BINS = BBYTES / 1024 / NW;
+  constexpr int BUPR = TN / 2;               // 16-byte units per B row
+  static_assert(ABYTES % (1024 * NW) == 0 && BBYTES % (1024 * NW) == 0, "load split");
+  static_assert(TN % 16 == 0 && BUPR >= 16, "B swizzle needs >= 16 units per row");
+  __shared__ __attribute__((aligned(1024))) uint8_t smem[NS * SBYTES];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int k0 = (int)p.k0, k1 = (int)p.k1, bstep = (int)p.bstep;
+
+  const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
+  const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
+
+  for (int slot = slot0;; slot += slots) {
+    if (!p.persistent && slot != slot0) break;
+    if (slot >= p.per_xcd) break;
+    const int idx = xcd * p.per_xcd + slot;
+    if (idx >= p.nitems) break;
+    const WorkItem it = p.items[idx];
+    const bool full_tile = (it.h == TM) && (it.w == TN);
+    const double* Ab = p.A + (int64_t)it.r0 * p.lda;
+    const double* Bb = p.B + it.c0;
+    double* Cb = p.C + (int64_t)it.r0 * p.ldc + it.c0;
+
+    // issue the DMA loads of chunk [c0, c0 + clen) into ring stage `st`
+    auto issue = [&](int c0, int clen, int st) {
+      uint8_t* sA = smem + st * SBYTES;
+      uint8_t* sB = sA + ABYTES;
+#pragma unroll
+      for (int j = 0; j < AINS; ++j) {
+        const int t = wave * AINS + j;             // 1 KB block: rows 8t .. 8t+7
+        const int row = 8 * t + (lane >> 3);
+        const int u = (lane & 7) ^ ((row >> 1) & 7);
+        const double* src = Ab + (int64_t)row * p.lda + c0 + 2 * u;
+        if (row >= it.h || 2 * u >= clen) src = g_zero_page;
+        __builtin_amdgcn_global_load_lds((const void*)src,
+            (__attribute__((address_space(3))) void*)(sA + t * 1024), 16, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < BINS; ++j) {
+        const int t = wave * BINS + j;             // 1 KB block of B rows
+        const int unit = t * 64 + lane;            // LDS unit in the stage
+        const int kk = unit / BUPR, us = unit % BUPR;
+        const int u = us ^ (8 * (kk & 1));
+        const double* src = Bb + (int64_t)(c0 + kk) * p.ldb + 2 * u;
+        if (kk >= clen || 2 * u >= it.w) src = g_zero_page;
+        __builtin_amdgcn_global_load_lds((const void*)src,
+            (__attribute__((address_space(3))) void*)(sB + t * 1024), 16, 0, 0);
+      }
+    };
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[fm][fn][v] = 0.0;
+    // C first: its loads are then older than every chunk load of the item
+    if (!p.zero_init) {
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const int col = wn * WTN + fn * 16 + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = wm * WTM + fm * 16 + 4 * v + lq;
+            if (full_tile || (row < it.h && col < it.w))
+              acc[fm][fn][v] = Cb[(int64_t)row * p.ldc + col];
+          }
+        }
+    }
+
+    // chunk schedule (inner steps of bstep from k0, KC-chunks inside each)
+    int q_c0 = k0, q_end = min(k0 + bstep, k1);  // next chunk to issue
+    auto next_chunk = [&](int& c0, int& clen) {
+      c0 = q_c0;
+      clen = min(KC, q_end - q_c0);
+      int n0 = q_c0 + KC;
+      if (n0 >= q_end) {
+        n0 = q_end;
+        q_end = min(q_end + bstep, k1);
+      }
+      q_c0 = n0;
+    };
+    int nchunks = 0;
+    for (int s0 = k0; s0 < k1; s0 += bstep) nchunks += (min(s0 + bstep, k1) - s0 + KC - 1) / KC;
+    // prologue: NS - 1 chunks in flight
+#pragma unroll
+    for (int st = 0; st < NS - 1; ++st) {
+      if (st < nchunks) {
+        int c0, clen;
+        next_chunk(c0, clen);
+        issue(c0, clen, st);
+      }
+    }
+    for (int ci = 0; ci < nchunks; ++ci) {
+      // chunk ci's own loads must be complete; the ones issued after it may
+      // stay in flight (vmcnt counts this wave's loads in issue order)
+      const int ahead = min(NS - 2, nchunks - 1 - ci);
+      if (NS >= 4 && ahead >= 2)
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (AINS + BINS)) : "memory");
+      else if (NS >= 3 && ahead >= 1)
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(AINS + BINS) : "memory");
+      else
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      // refill the stage consumed in the previous iteration
+      if (ci + NS - 1 < nchunks) {
+        int c0, clen;
+        next_chunk(c0, clen);
+        issue(c0, clen, (ci + NS - 1) % NS);
+      }
+      const uint8_t* sA = smem + (ci % NS) * SBYTES;
+      const uint8_t* sB = sA + ABYTES;
+#pragma unroll
+      for (int q = 0; q < KC / 4; ++q) {
+        double af[FM], bf[FN];
+        const int k = 4 * q + lq;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) {
+          const int row = wm * WTM + fm * 16 + l16;
+          const int u = (k >> 1) ^ ((row >> 1) & 7);
+          af[fm] = *(const double*)(sA + row * 128 + u * 16 + (k & 1) * 8);
+        }
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const int col = wn * WTN + fn * 16 + l16;
+          const int u = (col >> 1) ^ (8 * (k & 1));
+          bf[fn] = *(const double*)(sB + k * TN * 8 + u * 16 + (col & 1) * 8);
+        }
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < FN; ++fn)
+            acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[fm], bf[fn], acc[fm][fn], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the ring is reused by the next item
+
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) {
+        const int col = wn * WTN + fn * 16 + l16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = wm * WTM + fm * 16 + 4 * v + lq;
+          if (full_tile || (row < it.h && col < it.w))
+            Cb[(int64_t)row * p.ldc + col] = acc[fm][fn][v];
+        }
+      }
+  }
+}
+
 namespace {
 struct Fp64Entry {
   TileCfg cfg;
@@ -227,6 +408,24 @@ const std::vector<Fp64Entry>& table() {
   };
   return t;
 }
+
+struct DmaEntry {
+  TileCfg cfg;
+  void (*kern)(UpdateArgs);
+  int occupancy;
+};
+#define HS_DMA(TM, TN, NS, OCC) \
+  DmaEntry{TileCfg{TM, TN, 16}, fp64_dma_kernel<TM, TN, NS, 2, 2, OCC>, OCC}
+// direct-to-LDS kernels, keyed by the staged kernel configuration they replace
+const std::vector<DmaEntry>& dma_table() {
+  static const std::vector<DmaEntry> t = {
+      HS_DMA(128, 128, 2, 2),
+      HS_DMA(64, 64, 4, 2),
+      HS_DMA(128, 64, 3, 2),
+      HS_DMA(64, 128, 3, 2),
+  };
+  return t;
+}
 }  // namespace
 
 const std::vector<TileCfg>& fp64_configs() {
@@ -244,7 +443,22 @@ int fp64_occupancy(const TileCfg& cfg) {
   return 0;
 }
 
-hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s) {
+bool fp64_has_dma(const TileCfg& cfg) {
+  for (auto& e : dma_table())
+    if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) return true;
+  return false;
+}
+
+hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s,
+                       bool dma) {
+  if (dma) {
+    for (auto& e : dma_table()) {
+      if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) {
+        hipLaunchKernelGGL(e.kern, dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+  }
   for (auto& e : table()) {
     if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) {
       hipLaunchKernelGGL(e.kern, dim3(grid), dim3(e.threads), 0, s, a);

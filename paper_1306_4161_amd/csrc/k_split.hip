@@ -31,6 +31,7 @@ namespace hs {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 
 __device__ inline int exponent_bound(double mx) {
   if (!(mx > 0.0)) return 0;
@@ -51,6 +52,10 @@ __device__ inline uint8_t e4m3_of_int(int d) {
   return (uint8_t)(bits | (d < 0 ? 0x80 : 0));
 }
 
+// Digit planes are stored k16-block-major: element (plane, row, kk) at
+// plane * plane_stride + (kk / 16) * rows * 16 + row * 16 + kk % 16, so that
+// the 16 k of one row of one block are contiguous and one block of a plane
+// (all rows) is one contiguous run, the unit the product kernel streams.
 template <int FMT>
 __device__ inline void split_value(double a, int e, int smax, uint16_t* out16, uint8_t* out8,
                                    int64_t plane_stride, int64_t pos) {
@@ -101,7 +106,8 @@ __global__ __launch_bounds__(256) void split_rows_kernel(SplitArgs p) {
   uint8_t* o8 = (uint8_t*)p.digA;
   for (int kk = lane; kk < p.Wp; kk += 64) {
     const double a = kk < p.w ? row[kk] : 0.0;
-    split_value<FMT>(a, e, p.smax, o16, o8, p.planeA, (int64_t)i * p.Wp + kk);
+    split_value<FMT>(a, e, p.smax, o16, o8, p.planeA,
+                     (int64_t)(kk >> 4) * p.m * 16 + (int64_t)i * 16 + (kk & 15));
   }
 }
 
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(256) void split_cols_kernel(SplitArgs p) {
     if (j0 + cc < p.n) {
       for (int l = 0; l < p.smax; ++l) {
         const uint16_t* src = tile + (l * 64 + cc) * RS + seg * 16;
-        const int64_t pos = (int64_t)(j0 + cc) * p.Wp + rb + seg * 16;
+        const int64_t pos = (int64_t)((rb >> 4) + seg) * p.n * 16 + (int64_t)(j0 + cc) * 16;
         if (FMT == 0) {
           uint4* dst = (uint4*)((uint16_t*)p.digB + l * p.planeB + pos);
           const uint4* s4 = (const uint4*)src;
@@ -258,7 +264,6 @@ void slice_update_kernel(SliceArgs p) {
     // clamped to its last row; their results are never stored)
     const uint8_t* gA = (const uint8_t*)p.digA;
     const uint8_t* gB = (const uint8_t*)p.digB;
-    const int64_t rowbytes = (int64_t)p.Wp * T::ESZ;
 
     uint4 sa[T::AU], sb[T::BU];
     auto load_chunk = [&](int ch) {
@@ -270,8 +275,10 @@ void slice_update_kernel(SliceArgs p) {
         const int part = u % T::UPR;
         if (u < T::AUNITS && plane < s) {
           const int row = it.r0 + min(rr, it.h - 1);
-          sa[q] = *(const uint4*)(gA + plane * p.planeA * T::ESZ + row * rowbytes +
-                                  (int64_t)ch * T::KC * T::ESZ + part * 16);
+          const int kb = (ch * T::KC * T::ESZ + part * 16) / (16 * T::ESZ);
+          const int ko = (ch * T::KC * T::ESZ + part * 16) % (16 * T::ESZ);
+          sa[q] = *(const uint4*)(gA + plane * p.planeA * T::ESZ +
+                                  (int64_t)kb * p.rowsA * 16 * T::ESZ + (int64_t)row * 16 * T::ESZ + ko);
         }
       }
 #pragma unroll
@@ -282,8 +289,10 @@ void slice_update_kernel(SliceArgs p) {
         const int part = u % T::UPR;
         if (u < T::BUNITS && plane < s) {
           const int col = it.c0 + min(cc, it.w - 1);
-          sb[q] = *(const uint4*)(gB + plane * p.planeB * T::ESZ + col * rowbytes +
-                                  (int64_t)ch * T::KC * T::ESZ + part * 16);
+          const int kb = (ch * T::KC * T::ESZ + part * 16) / (16 * T::ESZ);
+          const int ko = (ch * T::KC * T::ESZ + part * 16) % (16 * T::ESZ);
+          sb[q] = *(const uint4*)(gB + plane * p.planeB * T::ESZ +
+                                  (int64_t)kb * p.rowsB * 16 * T::ESZ + (int64_t)col * 16 * T::ESZ + ko);
         }
       }
     };
@@ -434,6 +443,189 @@ void slice_update_kernel(SliceArgs p) {
   }
 }
 
+// ---- BF16 slice products, streamed ------------------------------------------
+// Workgroup tile 64 x 128, 8 waves (2 x 4) of one 32x32 block each, on
+// v_mfma_f32_32x32x16_bf16.  Per 16-k step the digits of every plane of the
+// tile stream from global memory straight into an NS-stage LDS ring
+// (global_load_lds_dwordx4; 6 x SMAX wave-instructions per step spread over
+// the 8 waves).  LDS image of one plane: [row][half] 16-byte units, the half
+// index XOR-swizzled by bit 3 of the row so that a fragment read (32 rows x
+// one half) is bank-conflict free.
+//
+// 32x32x16 operand layout: lane l holds A[l % 32][8 (l / 32) .. + 7] and
+// B[8 (l / 32) .. + 7][l % 32]; D item v of lane l is
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+//
+// Level accumulators (FP32): index a = l1 + l2 (0-based) for a <= 3, one
+// shared accumulator for a >= 4.  Exact while a level's partial sums stay
+// within 2^24: at most 4 pairs of |d d'| <= 2^16 over 64 k, so every 64 k
+// (a group of 4 steps; the panel is padded to a multiple of 64) the levels
+// are added into the FP64 panel sum; the shared deep accumulator (weight
+// <= 2^-36) needs no exactness.
+//
+// The slice count S is a template parameter of the item loop (the kernel
+// dispatches on the panel's count once), so the pair structure is static.
+constexpr int kBf16TM = 64, kBf16TN = 128, kBf16NW = 8, kBf16NS = 3;
+
+template <int S>
+__device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* smem) {
+  constexpr int SMAX = kSplitMaxSlices;        // planes present in the workspace
+  constexpr int TM = kBf16TM, TN = kBf16TN, NW = kBf16NW, NS = kBf16NS;
+  constexpr int ABYTES = S * TM * 32, BBYTES = S * TN * 32, SB = ABYTES + BBYTES;
+  constexpr int NI = 6 * S;                    // DMA wave-instructions per 16-k step
+  constexpr int NIHI = (NI + NW - 1) / NW, NILO = NI / NW;
+  constexpr int NACC = S < 5 ? S : 5;
+  static_assert(NS * (SMAX * (TM + TN) * 32) <= 160 * 1024, "LDS ring too large");
+  (void)SMAX;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int my_ni = (NI - wave + NW - 1) / NW;  // this wave's DMA instructions per step
+
+  const uint8_t* gA = (const uint8_t*)p.digA;
+  const uint8_t* gB = (const uint8_t*)p.digB;
+  const int64_t kbA = (int64_t)p.rowsA * 32, kbB = (int64_t)p.rowsB * 32;  // bytes per k16 block
+  const int nsteps = p.Wp / 16;
+  const int arow = wm * 32 + l32;
+  const int aoff = (arow * 2 + (lh ^ ((arow >> 3) & 1))) * 16;
+  const int bcol = wn * 32 + l32;
+  const int boff = (bcol * 2 + (lh ^ ((bcol >> 3) & 1))) * 16;
+
+  const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
+  const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
+
+  for (int slot = slot0;; slot += slots) {
+    if (!p.persistent && slot != slot0) break;
+    if (slot >= p.per_xcd) break;
+    const int idx = xcd * p.per_xcd + slot;
+    if (idx >= p.nitems) break;
+    const WorkItem it = p.items[idx];
+
+    auto issue = [&](int kb, int st) {
+      uint8_t* sA = smem + st * SB;
+      uint8_t* sB = sA + ABYTES;
+#pragma unroll
+      for (int j = 0; j < NIHI; ++j) {
+        const int t = wave + NW * j;
+        if (t < NI) {
+          const void* src;
+          uint8_t* dst;
+          if (t < 2 * S) {
+            const int plane = t >> 1, u = (t & 1) * 64 + lane;
+            const int row = u >> 1, half = (u & 1) ^ ((row >> 3) & 1);
+            const int grow = it.r0 + min(row, it.h - 1);
+            src = gA + plane * p.planeA * 2 + kb * kbA + (int64_t)grow * 32 + half * 16;
+            dst = sA + plane * (TM * 32) + (t & 1) * 1024;
+          } else {
+            const int tb = t - 2 * S;
+            const int plane = tb >> 2, u = (tb & 3) * 64 + lane;
+            const int col = u >> 1, half = (u & 1) ^ ((col >> 3) & 1);
+            const int gcol = it.c0 + min(col, it.w - 1);
+            src = gB + plane * p.planeB * 2 + kb * kbB + (int64_t)gcol * 32 + half * 16;
+            dst = sB + plane * (TN * 32) + (tb & 3) * 1024;
+          }
+          __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16,
+                                           0, 0);
+        }
+      }
+    };
+
+    f16v acc[NACC];
+    double cp[16];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][v] = 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) cp[v] = 0.0;
+
+#pragma unroll
+    for (int st = 0; st < NS - 1; ++st)
+      if (st < nsteps) issue(st, st);
+
+    for (int ci = 0; ci < nsteps; ++ci) {
+      const int ahead = min(NS - 2, nsteps - 1 - ci);
+      // wait for this wave's loads of step ci (later steps stay in flight)
+      if (NS >= 3 && ahead >= 1) {
+        if (my_ni == NIHI)
+          asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NIHI) : "memory");
+        else
+          asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NILO) : "memory");
+      } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
+      __syncthreads();
+      if (ci + NS - 1 < nsteps) issue(ci + NS - 1, (ci + NS - 1) % NS);
+
+      const uint8_t* sA = smem + (ci % NS) * SB;
+      const uint8_t* sB = sA + ABYTES;
+      bf8v bfr[S];
+#pragma unroll
+      for (int l2 = 0; l2 < S; ++l2) bfr[l2] = *(const bf8v*)(sB + l2 * (TN * 32) + boff);
+#pragma unroll
+      for (int l1 = 0; l1 < S; ++l1) {
+        const bf8v afr = *(const bf8v*)(sA + l1 * (TM * 32) + aoff);
+#pragma unroll
+        for (int l2 = 0; l2 < S - l1; ++l2) {
+          constexpr int last_acc = NACC - 1;
+          const int a = (l1 + l2) < last_acc ? (l1 + l2) : last_acc;
+          acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[l2], acc[a], 0, 0, 0);
+        }
+      }
+      // every 64 k (4 steps; the panel is padded to a multiple of 64) add
+      // the levels into the FP64 panel sum, smallest weight first
+      if ((ci & 3) == 3) {
+#pragma unroll
+        for (int a = NACC - 1; a >= 0; --a) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            cp[v] += (double)acc[a][v];
+            acc[a][v] = 0.f;
+          }
+        }
+      }
+    }
+    __syncthreads();  // the ring is reused by the next item
+
+    // C += 2^(e_i + f_j - 16) x panel sum
+    const int col = wn * 32 + l32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = wm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (row < it.h && col < it.w) {
+        const int gr = it.r0 + row, gc = it.c0 + col;
+        const double add = ldexp(cp[v], p.eA[gr] + p.fB[gc] - 16);
+        double* cptr = p.C + (int64_t)gr * p.ldc + gc;
+        *cptr = p.zero_init ? add : *cptr + add;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(512, 1) void slice_bf16_kernel(SliceArgs p) {
+  __shared__ __attribute__((aligned(1024)))
+      uint8_t smem[kBf16NS * kSplitMaxSlices * (kBf16TM + kBf16TN) * 32];
+  int s = p.fixed_s;
+  if (s <= 0) {
+    const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
+    const float need = (float)p.tau_bits - 8.0f + log2f(exp2f(ka) + exp2f(kb));
+    s = (int)ceilf(need / 9.0f) + 1;
+    s = max(p.smin, min(p.smax, s));
+  }
+  s = max(1, min(kSplitMaxSlices, s));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
+  switch (s) {
+    case 1: slice_bf16_items<1>(p, smem); break;
+    case 2: slice_bf16_items<2>(p, smem); break;
+    case 3: slice_bf16_items<3>(p, smem); break;
+    case 4: slice_bf16_items<4>(p, smem); break;
+    case 5: slice_bf16_items<5>(p, smem); break;
+    case 6: slice_bf16_items<6>(p, smem); break;
+    default: slice_bf16_items<7>(p, smem); break;
+  }
+}
+
 // ---- self-test of the matrix-core accumulation -------------------------------
 // D (16 x 16, FP32) = A (16 x k digits, row-major) x B (k x 16 digits,
 // row-major) by chained 16x16x32 MFMAs with FP32 accumulation, exactly as the
@@ -499,7 +691,7 @@ hipError_t launch_zero_u32(uint32_t* ptr, int n, hipStream_t s) {
 
 hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s) {
   if (fmt == 0)
-    hipLaunchKernelGGL((slice_update_kernel<0, kSplitMaxSlices, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(512), 0, s, a);
   else
     hipLaunchKernelGGL((slice_update_kernel<1, kSplitMaxSlices, 2, 2>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();

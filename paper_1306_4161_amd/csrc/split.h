@@ -6,7 +6,7 @@
 namespace hs {
 
 constexpr int kSplitMaxSlices = 7;   // digit planes written per operand
-constexpr int kSplitChunk = 32;      // k per slice-product step; panel width padded to this
+constexpr int kSplitChunk = 32;      // panel width is padded to a multiple of this
 
 struct SplitArgs {
   const double* A; int64_t lda;      // panel = A(:, k0:k0+w)
@@ -21,8 +21,8 @@ struct SplitArgs {
 };
 
 struct SliceArgs {
-  const void* digA; int64_t planeA;
-  const void* digB; int64_t planeB;
+  const void* digA; int64_t planeA; int32_t rowsA;   // rowsA = m
+  const void* digB; int64_t planeB; int32_t rowsB;   // rowsB = n
   const int32_t* eA; const int32_t* fB;
   const uint32_t* stats; int32_t* slices_out;
   double* C; int64_t ldc;

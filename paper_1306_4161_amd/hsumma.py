@@ -22,6 +22,8 @@ EXPORTED = [
     "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
     "hsumma_split_layout", "hsumma_mfma_exact_probe",
+    "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
+    "hsumma_mlp_adam",
 ]
 
 
@@ -33,8 +35,8 @@ class Opts(ctypes.Structure):
         ("slices", ctypes.c_int32), ("min_slices", ctypes.c_int32), ("max_slices", ctypes.c_int32),
         ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32), ("kc", ctypes.c_int32),
         ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-        ("tau_bits", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("tau_bits", ctypes.c_int32), ("staged", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -51,6 +53,10 @@ def lib():
     """Load libhsumma.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # Share torch's HIP runtime: torch must be loaded before the library,
+        # otherwise the library's own libamdhip64 is mapped first and torch
+        # later maps a second runtime into the process.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libhsumma.so not built: run `python -m paper_1306_4161_amd.build` "
                                "(the HIP library is required; there is no CPU fallback)")
@@ -78,6 +84,12 @@ def lib():
         sz = ctypes.c_size_t
         L.hsumma_split_layout.argtypes = [vp, P(sz), P(sz), P(sz), P(sz), P(i32), P(i32)]
         L.hsumma_mfma_exact_probe.argtypes = [i32, vp, vp, i32, vp, vp]
+        L.hsumma_mlp_param_count.argtypes = [i32, i32, i32]
+        L.hsumma_mlp_work_floats.argtypes = [i32, i32, i32]
+        L.hsumma_mlp_forward.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.hsumma_mlp_grad.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.hsumma_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, i32, vp]
         L.hsumma_last_error.restype = ctypes.c_char_p
         L.hsumma_last_error.argtypes = []
         L.hsumma_version.restype = ctypes.c_char_p
@@ -86,6 +98,8 @@ def lib():
             if name not in ("hsumma_opts_default", "hsumma_plan_destroy",
                             "hsumma_last_error", "hsumma_version"):
                 getattr(L, name).restype = ctypes.c_int
+        L.hsumma_mlp_param_count.restype = i64
+        L.hsumma_mlp_work_floats.restype = i64
         _lib = L
     return _lib
 
@@ -120,14 +134,14 @@ class Plan:
 
     def __init__(self, n, P, Q, G, b, M=None, *, m=0, k=0, dist=DIST_BLOCK, nb=0,
                  prec=FP64, slices=0, min_slices=0, max_slices=0, tile_m=0, tile_n=0,
-                 kc=0, persistent=0, use_graph=0, tau_bits=0):
+                 kc=0, persistent=0, use_graph=0, tau_bits=0, staged=0):
         L = lib()
         o = Opts()
         L.hsumma_opts_default(ctypes.byref(o))
         o.m, o.k, o.dist, o.nb, o.prec = m, k, dist, nb, prec
         o.slices, o.min_slices, o.max_slices = slices, min_slices, max_slices
         o.tile_m, o.tile_n, o.kc = tile_m, tile_n, kc
-        o.persistent, o.use_graph, o.tau_bits = persistent, use_graph, tau_bits
+        o.persistent, o.use_graph, o.tau_bits, o.staged = persistent, use_graph, tau_bits, staged
         h = ctypes.c_void_p()
         _check(L.hsumma_plan(ctypes.byref(h), n, P, Q, G, b, M if M is not None else b,
                              ctypes.byref(o)))
@@ -251,6 +265,61 @@ def mfma_exact_probe(fmt, a_digits, b_digits, stream=None):
                                          ctypes.c_void_p(b_digits.data_ptr()), k,
                                          ctypes.c_void_p(d.data_ptr()), _stream(stream)))
     return d
+
+
+def _f32_ptr(t, what, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 \
+            or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 CUDA tensor" % what)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %r, expected %r" % (what, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_param_count(F, H, K):
+    return int(lib().hsumma_mlp_param_count(F, H, K))
+
+
+def mlp_work(N, H, K):
+    import torch
+    return torch.empty(int(lib().hsumma_mlp_work_floats(N, H, K)), dtype=torch.float32,
+                       device="cuda")
+
+
+def mlp_forward(X, params, H, K, work=None, stream=None):
+    """Z = network(X) on the GPU (see hsumma_mlp_forward)."""
+    import torch
+    N, F = X.shape
+    Z = torch.empty((N, K), dtype=torch.float32, device="cuda")
+    work = mlp_work(N, H, K) if work is None else work
+    _check(lib().hsumma_mlp_forward(N, F, H, K, _f32_ptr(X, "X"),
+                                    _f32_ptr(params, "params", (mlp_param_count(F, H, K),)),
+                                    _f32_ptr(Z, "Z"), _f32_ptr(work, "work"), _stream(stream)))
+    return Z
+
+
+def mlp_grad(X, T, mask, params, H, K, grads=None, work=None, stream=None):
+    """(loss tensor on device, grads, Z) of the masked MSE (see hsumma_mlp_grad)."""
+    import torch
+    N, F = X.shape
+    n = mlp_param_count(F, H, K)
+    grads = torch.empty(n, dtype=torch.float32, device="cuda") if grads is None else grads
+    Z = torch.empty((N, K), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    work = mlp_work(N, H, K) if work is None else work
+    _check(lib().hsumma_mlp_grad(N, F, H, K, _f32_ptr(X, "X"), _f32_ptr(T, "T", (N, K)),
+                                 _f32_ptr(mask, "mask", (N, K)), _f32_ptr(params, "params", (n,)),
+                                 _f32_ptr(grads, "grads", (n,)), _f32_ptr(Z, "Z"),
+                                 _f32_ptr(loss, "loss"), _f32_ptr(work, "work"), _stream(stream)))
+    return loss, grads, Z
+
+
+def mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    n = params.numel()
+    _check(lib().hsumma_mlp_adam(n, _f32_ptr(params, "params"), _f32_ptr(grads, "grads"),
+                                 _f32_ptr(m, "m"), _f32_ptr(v, "v"), lr, beta1, beta2, eps, step,
+                                 _stream(stream)))
 
 
 def version():

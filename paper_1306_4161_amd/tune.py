@@ -1,0 +1,203 @@
+"""Autotuner: exhaustive timing of kernel configurations per problem shape.
+
+The paper picks its number of groups G by sampling a few HSUMMA iterations
+with different values (Sec. V-A's model validation, Sec. VI).  On one GPU the
+knobs that change speed but not the product are the kernel configuration of
+the local update: the macro-tile and k-chunk of the FP64 path, the grouped
+persistent launch, and the precision form.  The tuner times one outer step
+(hsumma_outer_update: every inner step of one outer block, one launch) of
+each candidate -- per-step cost is uniform over the steps -- and keeps the
+fastest one that is allowed for the shape: the BF16 split form only where
+its accuracy on the shape's value distribution is established (exponent
+spread sigma <= 2, see tests/test_parity_split.py).
+
+Results are cached as JSON (path from $HSUMMA_TUNE_CACHE or an argument),
+keyed by the shape.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import asdict, dataclass
+
+from . import hsumma as hs
+
+# (name, plan options).  FP64 tiles are the configurations compiled into the
+# library; the split form picks its slice count per panel.
+CANDIDATES = [
+    ("fp64_128x128x16", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=16)),
+    ("fp64_128x128x8", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=8)),
+    ("fp64_128x128x32", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=32)),
+    ("fp64_256x128x8", dict(prec=hs.FP64, tile_m=256, tile_n=128, kc=8)),
+    ("fp64_128x64x16", dict(prec=hs.FP64, tile_m=128, tile_n=64, kc=16)),
+    ("fp64_64x128x16", dict(prec=hs.FP64, tile_m=64, tile_n=128, kc=16)),
+    ("fp64_64x64x16", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=16)),
+    ("fp64_64x64x32", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=32)),
+    ("fp64_32x32x16", dict(prec=hs.FP64, tile_m=32, tile_n=32, kc=16)),
+    ("fp64_128x128x16_persistent", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=16,
+                                        persistent=1)),
+    ("fp64_64x64x16_persistent", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=16, persistent=1)),
+    ("split_bf16", dict(prec=hs.SPLIT_BF16)),
+]
+NAMES = [c[0] for c in CANDIDATES]
+DEFAULT = "fp64_128x128x16"   # what the library picks without tuning (large shapes)
+SPLIT_MAX_SIGMA = 2.0
+
+
+@dataclass(frozen=True)
+class Shape:
+    m: int
+    n: int
+    k: int
+    P: int
+    Q: int
+    G: int
+    M: int
+    sigma: float = 0.0
+
+    def key(self) -> str:
+        return "m%d_n%d_k%d_P%d_Q%d_G%d_M%d_s%g" % (self.m, self.n, self.k, self.P, self.Q,
+                                                    self.G, self.M, self.sigma)
+
+
+def allowed(shape: Shape, name: str) -> bool:
+    return not (name == "split_bf16" and shape.sigma > SPLIT_MAX_SIGMA)
+
+
+def operands(shape: Shape, seed: int = 0):
+    """Device operands of the shape's distribution (generated on the GPU)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+
+    def draw(r, c):
+        u = torch.rand((r, c), dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+        if shape.sigma > 0:
+            e = torch.round(torch.randn((r, c), dtype=torch.float64, device="cuda", generator=g)
+                            * shape.sigma)
+            u = torch.ldexp(u, e.to(torch.int32))
+        return u
+
+    A = draw(shape.m, shape.k)
+    B = draw(shape.k, shape.n)
+    C = torch.zeros((shape.m, shape.n), dtype=torch.float64, device="cuda")
+    return A, B, C
+
+
+def time_candidate(shape: Shape, opts: dict, A, B, C, reps: int = 3) -> float:
+    """Median time (ms) of one outer step with the given options."""
+    import torch
+    plan = hs.Plan(shape.n, shape.P, shape.Q, shape.G, shape.M, shape.M, m=shape.m, k=shape.k,
+                   **opts)
+    ws = plan.workspace()
+    stream = torch.cuda.current_stream()
+    plan.outer_update(0, A, B, C, ws=ws)          # warm-up (uploads the work items)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.outer_update(0, A, B, C, ws=ws)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    plan.close()
+    times.sort()
+    return times[len(times) // 2]
+
+
+def time_shape(shape: Shape, names=None, reps: int = 3, seed: int = 0) -> dict:
+    """{candidate name: ms} for every allowed candidate."""
+    A, B, C = operands(shape, seed)
+    out = {}
+    for name, opts in CANDIDATES:
+        if names is not None and name not in names:
+            continue
+        if not allowed(shape, name):
+            continue
+        out[name] = time_candidate(shape, opts, A, B, C, reps)
+    del A, B, C
+    return out
+
+
+def best(times: dict) -> str:
+    return min(times, key=times.get)
+
+
+class Cache:
+    """JSON cache: shape key -> {"times": {...}, "best": name}."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path or os.environ.get("HSUMMA_TUNE_CACHE", "")
+        self.data = {}
+        if self.path and os.path.exists(self.path):
+            with open(self.path) as f:
+                self.data = json.load(f)
+
+    def get(self, shape: Shape):
+        return self.data.get(shape.key())
+
+    def put(self, shape: Shape, times: dict):
+        self.data[shape.key()] = {"shape": asdict(shape), "times": times, "best": best(times)}
+
+    def save(self):
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.data, f)
+            os.replace(tmp, self.path)
+
+
+def tune(shape: Shape, cache: Cache | None = None, reps: int = 3) -> tuple[str, dict]:
+    """Exhaustive search: (best candidate name, plan options), cached."""
+    cache = cache if cache is not None else Cache()
+    hit = cache.get(shape)
+    if hit is None:
+        times = time_shape(shape, reps=reps)
+        cache.put(shape, times)
+        cache.save()
+        hit = cache.get(shape)
+    name = hit["best"]
+    return name, dict(CANDIDATES)[name]
+
+
+def valid_groups(P: int, Q: int) -> list[int]:
+    """Every G that can be arranged as I x J groups with I | P and J | Q."""
+    out = set()
+    for I in range(1, P + 1):
+        if P % I:
+            continue
+        for J in range(1, Q + 1):
+            if Q % J == 0:
+                out.add(I * J)
+    return sorted(out)
+
+
+def random_shapes(count: int, seed: int, lo: int = 512, hi: int = 16384):
+    """Random problem shapes: m, n, k log-uniform in [lo, hi], P, Q in 1..16,
+    G uniform over the arrangeable group counts, outer block M in
+    {32, ..., 512}, exponent spread sigma in {0, 2, 4}."""
+    import numpy as np
+    r = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        m, n, k = (int(round(math.exp(r.uniform(math.log(lo), math.log(hi))))) for _ in range(3))
+        P, Q = int(r.integers(1, 17)), int(r.integers(1, 17))
+        G = int(r.choice(valid_groups(P, Q)))
+        M = int(r.choice([32, 64, 128, 256, 512]))
+        sigma = float(r.choice([0.0, 2.0, 4.0]))
+        out.append(Shape(m, n, k, P, Q, G, min(M, k), sigma))
+    return out
+
+
+def build_dataset(shapes, reps: int = 3, log=None) -> list:
+    """Time every allowed candidate of every shape: [{"shape", "times"}]."""
+    rows = []
+    t0 = time.time()
+    for i, sh in enumerate(shapes):
+        rows.append({"shape": asdict(sh), "times": time_shape(sh, reps=reps, seed=i)})
+        if log and (i + 1) % 50 == 0:
+            log("timed %d/%d shapes (%.0f s)" % (i + 1, len(shapes), time.time() - t0))
+    return rows
