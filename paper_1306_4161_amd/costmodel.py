@@ -131,9 +131,10 @@ def summarize(rg: np.ndarray) -> dict:
             "frac_optimal": float(np.mean(rg <= 1e-9))}
 
 
-def experiment(n_shapes: int, seed: int, n_test: int = 200, epochs: int = 2000, log=print):
+def experiment(n_shapes: int, seed: int, n_test: int = 200, epochs: int = 2000, log=print,
+               lo: int = 512, hi: int = 16384):
     """Dataset -> train on n_shapes - n_test -> regret on the held-out shapes."""
-    shapes = tune.random_shapes(n_shapes, seed)
+    shapes = tune.random_shapes(n_shapes, seed, lo=lo, hi=hi)
     t0 = time.time()
     rows = tune.build_dataset(shapes, log=log)
     t_label = time.time() - t0

@@ -387,7 +387,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     p->cfg = scfg;
     if (!p->opts.min_slices) p->opts.min_slices = 3;
     if (!p->opts.max_slices) p->opts.max_slices = hs::kSplitMaxSlices;
-    if (!p->opts.tau_bits) p->opts.tau_bits = 51;
+    if (!p->opts.tau_bits) p->opts.tau_bits = 48;
     const int smin = p->opts.min_slices, smax = p->opts.max_slices, sf = p->opts.slices;
     if (smin < 1 || smax > hs::kSplitMaxSlices || smin > smax || sf < 0 ||
         sf > hs::kSplitMaxSlices) {

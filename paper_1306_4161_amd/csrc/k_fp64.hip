@@ -250,30 +250,53 @@ void fp64_dma_kernel(UpdateArgs p) {
     const double* Bb = p.B + it.c0;
     double* Cb = p.C + (int64_t)it.r0 * p.ldc + it.c0;
 
+    // Per-item DMA sources (chunk offset 0) of this wave's instructions;
+    // a chunk at k-offset c0 adds c0 doubles to A sources and c0 rows to B
+    // sources.  Lanes whose unit lies outside the item read the zero page
+    // (and do not move with the chunk).
+    const double* asrc[AINS];
+    const double* bsrc[BINS];
+    bool aok[AINS], bok[BINS];
+    int bkk[BINS], au2[AINS];
+#pragma unroll
+    for (int j = 0; j < AINS; ++j) {
+      const int t = wave * AINS + j;               // 1 KB block: rows 8t .. 8t+7
+      const int row = 8 * t + (lane >> 3);
+      const int u = (lane & 7) ^ ((row >> 1) & 7);
+      aok[j] = row < it.h;
+      au2[j] = 2 * u;
+      asrc[j] = aok[j] ? Ab + (int64_t)row * p.lda + 2 * u : g_zero_page;
+    }
+#pragma unroll
+    for (int j = 0; j < BINS; ++j) {
+      const int t = wave * BINS + j;               // 1 KB block of B rows
+      const int unit = t * 64 + lane;              // LDS unit in the stage
+      const int kk = unit / BUPR, us = unit % BUPR;
+      const int u = us ^ (8 * (kk & 1));
+      bok[j] = 2 * u < it.w;
+      bkk[j] = kk;
+      bsrc[j] = bok[j] ? Bb + (int64_t)kk * p.ldb + 2 * u : g_zero_page;
+    }
     // issue the DMA loads of chunk [c0, c0 + clen) into ring stage `st`
     auto issue = [&](int c0, int clen, int st) {
       uint8_t* sA = smem + st * SBYTES;
       uint8_t* sB = sA + ABYTES;
+      const int64_t boffs = (int64_t)c0 * p.ldb;
 #pragma unroll
       for (int j = 0; j < AINS; ++j) {
-        const int t = wave * AINS + j;             // 1 KB block: rows 8t .. 8t+7
-        const int row = 8 * t + (lane >> 3);
-        const int u = (lane & 7) ^ ((row >> 1) & 7);
-        const double* src = Ab + (int64_t)row * p.lda + c0 + 2 * u;
-        if (row >= it.h || 2 * u >= clen) src = g_zero_page;
+        const double* src = asrc[j];
+        if (aok[j]) src += c0;
+        if (clen < KC && au2[j] >= clen) src = g_zero_page;
         __builtin_amdgcn_global_load_lds((const void*)src,
-            (__attribute__((address_space(3))) void*)(sA + t * 1024), 16, 0, 0);
+            (__attribute__((address_space(3))) void*)(sA + (wave * AINS + j) * 1024), 16, 0, 0);
       }
 #pragma unroll
       for (int j = 0; j < BINS; ++j) {
-        const int t = wave * BINS + j;             // 1 KB block of B rows
-        const int unit = t * 64 + lane;            // LDS unit in the stage
-        const int kk = unit / BUPR, us = unit % BUPR;
-        const int u = us ^ (8 * (kk & 1));
-        const double* src = Bb + (int64_t)(c0 + kk) * p.ldb + 2 * u;
-        if (kk >= clen || 2 * u >= it.w) src = g_zero_page;
+        const double* src = bsrc[j];
+        if (bok[j]) src += boffs;
+        if (clen < KC && bkk[j] >= clen) src = g_zero_page;
         __builtin_amdgcn_global_load_lds((const void*)src,
-            (__attribute__((address_space(3))) void*)(sB + t * 1024), 16, 0, 0);
+            (__attribute__((address_space(3))) void*)(sB + (wave * BINS + j) * 1024), 16, 0, 0);
       }
     };
 

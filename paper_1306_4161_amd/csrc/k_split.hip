@@ -24,6 +24,8 @@
 // level is exact over the whole panel (7 pairs x 2^8 x w <= 2^24 for
 // w <= 9362) and is added, scaled by 2^(-T (L - 2)), at the end of the panel.
 // Finally C += 2^(e_i + f_j - 2H) x panel sum, in FP64.
+#include <type_traits>
+
 #include "internal.h"
 #include "split.h"
 
@@ -77,37 +79,70 @@ __device__ inline void split_value(double a, int e, int smax, uint16_t* out16, u
   }
 }
 
-// ---- A rows: one wave per row ------------------------------------------------
+// ---- A rows: one half-wave per row ----------------------------------------------
+// Each lane owns 8 consecutive k of every 256-k piece of the row and writes
+// its digits of one plane as one 16-byte (BF16) or 8-byte (FP8) group.
 template <int FMT>
 __global__ __launch_bounds__(256) void split_rows_kernel(SplitArgs p) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wave;
-  if (i >= p.m) return;  // whole wave leaves; this kernel has no barrier
+  constexpr int H = FMT == 0 ? 8 : 4;
+  constexpr int T = FMT == 0 ? 9 : 5;
+  const int hw = threadIdx.x >> 5, hl = threadIdx.x & 31;
+  const int i = blockIdx.x * 8 + hw;
+  if (i >= p.m) return;  // the half-wave leaves; shuffles below stay inside a half-wave
   const double* row = p.A + (int64_t)i * p.lda + p.k0;
   double mx = 0.0, sm = 0.0;
-  for (int kk = lane; kk < p.w; kk += 64) {
-    const double a = fabs(row[kk]);
-    mx = fmax(mx, a);
-    sm += a;
+  for (int kk = hl * 8; kk < p.w; kk += 256) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (kk + e < p.w) {
+        const double a = fabs(row[kk + e]);
+        mx = fmax(mx, a);
+        sm += a;
+      }
+    }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, o));
-    sm += __shfl_xor(sm, o);
+  for (int o = 16; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 32));
+    sm += __shfl_xor(sm, o, 32);
   }
   const int e = exponent_bound(mx);
-  if (lane == 0) {
+  if (hl == 0) {
     p.eA[i] = e;
     if (sm > 0.0) {
       const float kap = (float)log2(mx * (double)p.w / sm);
       atomicMax(&p.stats[0], __float_as_uint(fmaxf(kap, 0.0f)));
     }
   }
-  uint16_t* o16 = (uint16_t*)p.digA;
-  uint8_t* o8 = (uint8_t*)p.digA;
-  for (int kk = lane; kk < p.Wp; kk += 64) {
-    const double a = kk < p.w ? row[kk] : 0.0;
-    split_value<FMT>(a, e, p.smax, o16, o8, p.planeA,
-                     (int64_t)(kk >> 4) * p.m * 16 + (int64_t)i * 16 + (kk & 15));
+  const int64_t blk = (int64_t)p.m * 16;     // elements per k16 block of a plane
+  for (int kk = hl * 8; kk < p.Wp; kk += 256) {
+    double r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = ldexp(kk + q < p.w ? row[kk + q] : 0.0, -e);
+    const int64_t pos = (int64_t)(kk >> 4) * blk + (int64_t)i * 16 + (kk & 15);
+    int shift = H;
+    for (int l = 0; l < p.smax; ++l) {
+      uint32_t w32[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double y = ldexp(r[q], shift);
+        const double d = rint(y);
+        r[q] = y - d;
+        uint32_t bits;
+        if (FMT == 0)
+          bits = __float_as_uint((float)ldexp(d, -T * l)) >> 16;  // d 2^(-T l), exact
+        else
+          bits = e4m3_of_int((int)d);
+        if (FMT == 0)
+          w32[q >> 1] |= bits << (16 * (q & 1));
+        else
+          w32[q >> 2] |= bits << (8 * (q & 3));
+      }
+      shift = T;
+      if (FMT == 0)
+        *(uint4*)((uint16_t*)p.digA + l * p.planeA + pos) = make_uint4(w32[0], w32[1], w32[2], w32[3]);
+      else
+        *(uint2*)((uint8_t*)p.digA + l * p.planeA + pos) = make_uint2(w32[0], w32[1]);
+    }
   }
 }
 
@@ -458,24 +493,30 @@ void slice_update_kernel(SliceArgs p) {
 //
 // Level accumulators (FP32): index a = l1 + l2 (0-based) for a <= 3, one
 // shared accumulator for a >= 4.  Exact while a level's partial sums stay
-// within 2^24: at most 4 pairs of |d d'| <= 2^16 over 64 k, so every 64 k
-// (a group of 4 steps; the panel is padded to a multiple of 64) the levels
-// are added into the FP64 panel sum; the shared deep accumulator (weight
-// <= 2^-36) needs no exactness.
+// within 2^24: a level of a + 1 pairs of |d d'| <= 2^16 may run 256/(a+1) k,
+// so levels 0, 1, 2-3 are added into the FP64 panel sum every 256, 128, 64 k
+// (the panel is padded to a multiple of 64); the shared deep accumulator
+// (weight <= 2^-36) needs no exactness and is added every 256 k.
 //
 // The slice count S is a template parameter of the item loop (the kernel
 // dispatches on the panel's count once), so the pair structure is static.
-constexpr int kBf16TM = 64, kBf16TN = 128, kBf16NW = 8, kBf16NS = 3;
+constexpr int kBf16TM = 64, kBf16TN = 128, kBf16NW = 8;
+constexpr int kBf16Lds = 152 * 1024;  // LDS ring budget (bytes)
+// ring depth for S planes: as many 16-k stages as fit, at most 5
+constexpr int bf16_stages(int S) {
+  return (kBf16Lds / (S * (kBf16TM + kBf16TN) * 32)) < 5 ? (kBf16Lds / (S * (kBf16TM + kBf16TN) * 32))
+                                                          : 5;
+}
 
 template <int S>
 __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* smem) {
   constexpr int SMAX = kSplitMaxSlices;        // planes present in the workspace
-  constexpr int TM = kBf16TM, TN = kBf16TN, NW = kBf16NW, NS = kBf16NS;
+  constexpr int TM = kBf16TM, TN = kBf16TN, NW = kBf16NW, NS = bf16_stages(S);
   constexpr int ABYTES = S * TM * 32, BBYTES = S * TN * 32, SB = ABYTES + BBYTES;
   constexpr int NI = 6 * S;                    // DMA wave-instructions per 16-k step
   constexpr int NIHI = (NI + NW - 1) / NW, NILO = NI / NW;
   constexpr int NACC = S < 5 ? S : 5;
-  static_assert(NS * (SMAX * (TM + TN) * 32) <= 160 * 1024, "LDS ring too large");
+  static_assert(NS >= 3 && NS * (S * (TM + TN) * 32) <= kBf16Lds, "LDS ring");
   (void)SMAX;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -502,32 +543,39 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
     if (idx >= p.nitems) break;
     const WorkItem it = p.items[idx];
 
+    // This wave's DMA sources for k16 block 0 (per-item constants); block kb
+    // adds kb x (rows x 32 bytes).  LDS destinations are uniform.
+    const uint8_t* src0[NIHI];
+    int64_t kstride[NIHI];
+    int dst_off[NIHI];
+#pragma unroll
+    for (int j = 0; j < NIHI; ++j) {
+      const int t = min(wave + NW * j, NI - 1);
+      if (t < 2 * S) {
+        const int plane = t >> 1, u = (t & 1) * 64 + lane;
+        const int row = u >> 1, half = (u & 1) ^ ((row >> 3) & 1);
+        const int grow = it.r0 + min(row, it.h - 1);
+        src0[j] = gA + plane * p.planeA * 2 + (int64_t)grow * 32 + half * 16;
+        kstride[j] = kbA;
+        dst_off[j] = plane * (TM * 32) + (t & 1) * 1024;
+      } else {
+        const int tb = t - 2 * S;
+        const int plane = tb >> 2, u = (tb & 3) * 64 + lane;
+        const int col = u >> 1, half = (u & 1) ^ ((col >> 3) & 1);
+        const int gcol = it.c0 + min(col, it.w - 1);
+        src0[j] = gB + plane * p.planeB * 2 + (int64_t)gcol * 32 + half * 16;
+        kstride[j] = kbB;
+        dst_off[j] = ABYTES + plane * (TN * 32) + (tb & 3) * 1024;
+      }
+    }
     auto issue = [&](int kb, int st) {
-      uint8_t* sA = smem + st * SB;
-      uint8_t* sB = sA + ABYTES;
+      uint8_t* stage = smem + st * SB;
 #pragma unroll
       for (int j = 0; j < NIHI; ++j) {
-        const int t = wave + NW * j;
-        if (t < NI) {
-          const void* src;
-          uint8_t* dst;
-          if (t < 2 * S) {
-            const int plane = t >> 1, u = (t & 1) * 64 + lane;
-            const int row = u >> 1, half = (u & 1) ^ ((row >> 3) & 1);
-            const int grow = it.r0 + min(row, it.h - 1);
-            src = gA + plane * p.planeA * 2 + kb * kbA + (int64_t)grow * 32 + half * 16;
-            dst = sA + plane * (TM * 32) + (t & 1) * 1024;
-          } else {
-            const int tb = t - 2 * S;
-            const int plane = tb >> 2, u = (tb & 3) * 64 + lane;
-            const int col = u >> 1, half = (u & 1) ^ ((col >> 3) & 1);
-            const int gcol = it.c0 + min(col, it.w - 1);
-            src = gB + plane * p.planeB * 2 + kb * kbB + (int64_t)gcol * 32 + half * 16;
-            dst = sB + plane * (TN * 32) + (tb & 3) * 1024;
-          }
-          __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16,
-                                           0, 0);
-        }
+        if (wave + NW * j < NI)
+          __builtin_amdgcn_global_load_lds(src0[j] + kb * kstride[j],
+                                           (__attribute__((address_space(3))) void*)(stage + dst_off[j]),
+                                           16, 0, 0);
       }
     };
 
@@ -544,40 +592,72 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
     for (int st = 0; st < NS - 1; ++st)
       if (st < nsteps) issue(st, st);
 
+    // Levels are added into the FP64 panel sum at their exactness cadence
+    // (period in 16-k steps): a = 0 every 16, a = 1 every 8, a = 2, 3 every
+    // 4, the shared deep accumulator every 16.
+    constexpr int PER[5] = {16, 8, 4, 4, 16};
     for (int ci = 0; ci < nsteps; ++ci) {
       const int ahead = min(NS - 2, nsteps - 1 - ci);
       // wait for this wave's loads of step ci (later steps stay in flight)
-      if (NS >= 3 && ahead >= 1) {
-        if (my_ni == NIHI)
-          asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NIHI) : "memory");
-        else
-          asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NILO) : "memory");
+      // (vmcnt counts this wave's DMA instructions in issue order; `ahead`
+      // later steps of my_ni instructions each may stay outstanding)
+      if (my_ni == NIHI) {
+        if (ahead >= 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * NIHI) : "memory");
+        else if (ahead == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * NIHI) : "memory");
+        else if (ahead == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NIHI) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       } else {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (ahead >= 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * NILO) : "memory");
+        else if (ahead == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * NILO) : "memory");
+        else if (ahead == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NILO) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       }
       __syncthreads();
       if (ci + NS - 1 < nsteps) issue(ci + NS - 1, (ci + NS - 1) % NS);
 
       const uint8_t* sA = smem + (ci % NS) * SB;
       const uint8_t* sB = sA + ABYTES;
-      bf8v bfr[S];
+      constexpr int last_acc = NACC - 1;
+      if (S <= 6) {
+        // fragments are read in the order A0, B0, A1, B1, ... and the pairs
+        // run level by level, so each level needs one new A and one new B
+        // fragment and the LDS latency hides behind the earlier levels
+        bf8v afr[S], bfr[S];
 #pragma unroll
-      for (int l2 = 0; l2 < S; ++l2) bfr[l2] = *(const bf8v*)(sB + l2 * (TN * 32) + boff);
+        for (int l = 0; l < S; ++l) {
+          afr[l] = *(const bf8v*)(sA + l * (TM * 32) + aoff);
+          bfr[l] = *(const bf8v*)(sB + l * (TN * 32) + boff);
+        }
 #pragma unroll
-      for (int l1 = 0; l1 < S; ++l1) {
-        const bf8v afr = *(const bf8v*)(sA + l1 * (TM * 32) + aoff);
+        for (int L = 0; L < S; ++L) {
 #pragma unroll
-        for (int l2 = 0; l2 < S - l1; ++l2) {
-          constexpr int last_acc = NACC - 1;
-          const int a = (l1 + l2) < last_acc ? (l1 + l2) : last_acc;
-          acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[l2], acc[a], 0, 0, 0);
+          for (int l1 = 0; l1 <= L; ++l1) {
+            const int a = L < last_acc ? L : last_acc;
+            acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[l1], bfr[L - l1], acc[a], 0, 0, 0);
+          }
+        }
+      } else {
+        // seven planes: keep every B fragment, stream the A fragments (fewer
+        // live registers)
+        bf8v bfr[S];
+#pragma unroll
+        for (int l2 = 0; l2 < S; ++l2) bfr[l2] = *(const bf8v*)(sB + l2 * (TN * 32) + boff);
+#pragma unroll
+        for (int l1 = 0; l1 < S; ++l1) {
+          const bf8v afr = *(const bf8v*)(sA + l1 * (TM * 32) + aoff);
+#pragma unroll
+          for (int l2 = 0; l2 < S - l1; ++l2) {
+            const int a = (l1 + l2) < last_acc ? (l1 + l2) : last_acc;
+            acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[l2], acc[a], 0, 0, 0);
+          }
         }
       }
-      // every 64 k (4 steps; the panel is padded to a multiple of 64) add
-      // the levels into the FP64 panel sum, smallest weight first
-      if ((ci & 3) == 3) {
+      const bool last = ci + 1 == nsteps;
+      const int nxt = ci + 1;
 #pragma unroll
-        for (int a = NACC - 1; a >= 0; --a) {
+      for (int a = NACC - 1; a >= 0; --a) {
+        const int per = PER[a < 4 ? a : 4];
+        if (last || (nxt % per) == 0) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             cp[v] += (double)acc[a][v];
@@ -604,8 +684,7 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
 }
 
 __global__ __launch_bounds__(512, 1) void slice_bf16_kernel(SliceArgs p) {
-  __shared__ __attribute__((aligned(1024)))
-      uint8_t smem[kBf16NS * kSplitMaxSlices * (kBf16TM + kBf16TN) * 32];
+  __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
   int s = p.fixed_s;
   if (s <= 0) {
     const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
@@ -672,7 +751,7 @@ hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float
 
 // ---- launchers ----------------------------------------------------------------
 hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
-  const int gr = (a.m + 3) / 4, gc = (a.n + 63) / 64;
+  const int gr = (a.m + 7) / 8, gc = (a.n + 63) / 64;
   if (a.fmt == 0) {
     hipLaunchKernelGGL(split_rows_kernel<0>, dim3(gr), dim3(256), 0, s, a);
     hipLaunchKernelGGL(split_cols_kernel<0>, dim3(gc), dim3(256), 0, s, a);

@@ -33,7 +33,8 @@ def test_exhaustive_tune_and_cache(tmp_path):
 
 
 def test_learned_model_beats_default_on_held_out_shapes():
-    res = costmodel.experiment(n_shapes=90, seed=7, n_test=30, epochs=800, log=None)
+    res = costmodel.experiment(n_shapes=90, seed=7, n_test=30, epochs=800, log=None,
+                               lo=256, hi=4096)
     print(json.dumps({k: res[k] for k in ("regret_mlp", "regret_default", "best_static")}))
     assert res["regret_mlp"]["mean"] < res["regret_default"]["mean"]
     assert np.isfinite(res["regret_mlp"]["max"])
