@@ -1,21 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the Hierarchical SUMMA local update on one MI355X.
 
-One "step" is one pass of the whole hot path over the workload: all
-k/b local updates of an HSUMMA product C = A x B (hsumma_run), with the
-operands already resident in HBM.  Workload (the size the headline metric is
-quoted at): n = 16384, 16 x 16 virtual grid, G = 16 groups (4 x 4 of 4 x 4),
-b = M = 256, FP64 entries U[-1, 1] (seeded, synthetic).
+One "step" is one pass of the whole hot path over the workload: every local
+update of an HSUMMA product C = A x B (hsumma_run: all k/b inner steps, in
+k/M outer steps), operands already resident in HBM.
 
-Prints one JSON line.  `value` is FP64-accurate GFLOP/s = 2 n^3 / t of the
-reported path.  `roofline` describes the dominant kernel (the update), whose
-average launch duration is measured with HIP events on the stream it is
-launched on.  `cpu_baseline` times the CPU oracle (plain FP64 triple loop)
-on a bounded slice of the same product.
+Workload (the size the headline metric is quoted at): n = 16384 FP64, a
+16 x 16 virtual grid, G = 16 groups (4 x 4 groups of 4 x 4 processors),
+inner block b = 256, outer block M = 1024 (= n/Q, the widest outer panel
+owned by one processor column), entries u * 2^e with u ~ U[-1, 1] and
+e = rint(N(0, sigma^2 = 4)) (seeded, synthetic).
+
+Paths timed: FP64-MFMA, and the BF16 digit split (slice count chosen per
+panel) -- both FP64-accurate (checked on sampled entries against the Dot2
+oracle: max |c_hat - c| / (|A||B|)_ij <= 1e-14) -- and the FP8-e4m3 split
+(reported, not FP64-accurate).  `value` is the FP64-accurate GFLOP/s
+(2 n^3 / t) of the fastest accurate path; `paths` holds every path.
+
+`roofline` describes the dominant kernel of the reported path: its
+algorithmic flops per launch over its average launch duration, measured with
+HIP events on the stream it runs on.  `traffic` is the HBM bytes per launch
+from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of that kernel
+(scaled by a copy-kernel calibration), or null if the kernel source changed
+since the counters were taken.  `cpu_baseline` times the CPU oracle (plain
+FP64 triple loop) on a bounded slice of the same product.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,10 +39,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 MFMA
-PEAK_BF16_TFLOPS = 2516.6    # MI355X dense BF16 MFMA
-PEAK_FP8_TFLOPS = 5033.2     # MI355X dense FP8 MFMA
-PEAK_HBM_GBS = 8000.0
+PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 MFMA
+PEAK_BF16 = 2516.6    # TFLOP/s, dense BF16 MFMA
+PEAK_FP8 = 5033.2     # TFLOP/s, dense FP8 MFMA
+GATE = 1e-14
 
 
 def log(msg):
@@ -39,28 +52,56 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--P", type=int, default=16)
     ap.add_argument("--Q", type=int, default=16)
     ap.add_argument("--G", type=int, default=16)
     ap.add_argument("--b", type=int, default=256)
-    ap.add_argument("--M", type=int, default=256)
-    ap.add_argument("--tile", type=str, default="")
+    ap.add_argument("--M", type=int, default=1024)
+    ap.add_argument("--sigma", type=float, default=2.0)
+    ap.add_argument("--paths", type=str, default="fp64,bf16,fp8")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=512)
     return ap.parse_args()
 
 
+def source_hash(*names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_1306_4161_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel: str, workload: str, src_hash: str):
+    """HBM bytes per launch from profiles/traffic_<kernel>_<workload>.txt, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(A, B, target_s):
-    """Time the oracle's plain triple loop on the first r rows of the product."""
+    """Time the oracle's plain triple loop on the first rows of the product."""
     from oracle import core
     core.build()
-    n = B.shape[1]
-    k = A.shape[1]
-    r = 4
+    n, k = B.shape[1], A.shape[1]
+    r = 8
     t0 = time.perf_counter()
     core.gemm(A[:r], B)
     dt = time.perf_counter() - t0
@@ -68,103 +109,149 @@ def cpu_baseline(A, B, target_s):
     t0 = time.perf_counter()
     core.gemm(A[:rows], B)
     dt = time.perf_counter() - t0
-    gflops = 2.0 * rows * n * k / dt / 1e9
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": core.threads(),
-            "kind": "oracle",
-            "sample": "rows 0..%d of C (%d x %d x %d FP64 triple loop, %.1f s)" % (
+    return {"value": round(2.0 * rows * n * k / dt / 1e9, 3), "unit": "GFLOP/s",
+            "cores": core.threads(), "kind": "oracle",
+            "sample": "rows 0..%d of C: %d x %d x %d plain FP64 triple loop (%.1f s)" % (
                 rows - 1, rows, k, n, dt)}
+
+
+def time_region(fn, steps, stream):
+    """ms per call of fn over `steps` calls, HIP events on `stream`."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the local update of all "
-              "virtual processors on a single MI355X (no multi-GPU path); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the local updates of every virtual processor run "
+              "on a single MI355X and there is no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    from oracle import core
     from paper_1306_4161_amd import hsumma as hs
     from paper_1306_4161_amd import inputs
 
     n, P, Q, G, b, M = args.n, args.P, args.Q, args.G, args.b, args.M
-    tile = {}
-    if args.tile:
-        tm, tn, kc = (int(x) for x in args.tile.split(","))
-        tile = dict(tile_m=tm, tile_n=tn, kc=kc)
-    log("generating operands n=%d" % n)
-    A = inputs.uniform(n, n, inputs.SEED_A)
-    B = inputs.uniform(n, n, inputs.SEED_B)
+    wl = "n%d" % n
+    log("generating operands n=%d sigma=%g" % (n, args.sigma))
+    if args.sigma > 0:
+        A = inputs.exponent_spread(n, n, inputs.SEED_A, args.sigma)
+        B = inputs.exponent_spread(n, n, inputs.SEED_B, args.sigma)
+    else:
+        A = inputs.uniform(n, n, inputs.SEED_A)
+        B = inputs.uniform(n, n, inputs.SEED_B)
     dA = torch.from_numpy(A).cuda()
     dB = torch.from_numpy(B).cuda()
     dC = torch.empty((n, n), dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
-
-    plan = hs.Plan(n, P, Q, G, b, M, **tile)
-    nouter = plan.num_outer_steps
-    log("plan: groups=%r steps=%d outer=%d items=%d" % (plan.groups, plan.num_steps, nouter,
-                                                         plan.num_items))
-    ws = plan.workspace()
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            plan.run(dA, dB, dC, ws=ws, stream=stream)
-    torch.cuda.synchronize()
-    log("warmup done")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        ev0.record(stream)
-        for _ in range(args.steps):
-            plan.run(dA, dB, dC, ws=ws, stream=stream)
-        ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    log("timed %d steps: %.3f ms/step (wall %.3f s)" % (args.steps, ms, wall))
-    flops = 2.0 * n * n * n
-    gflops = flops / (ms * 1e-3) / 1e9
-    # Dominant kernel: the update; one launch per outer step.
-    launches = nouter
-    per_launch_flops = 2.0 * n * n * M
-    avg_launch_ms = ms / launches
-    achieved = per_launch_flops / (avg_launch_ms * 1e-3) / 1e12
-
-    # Accuracy on sampled entries (scaled error |c_hat - c| / (|A||B|)_ij).
-    from oracle import core
     rows, cols = inputs.sample_entries(n, n, args.samples, inputs.SEED_SAMPLE)
-    C = dC.cpu().numpy()
     cref, sref = core.sampled(A, B, rows, cols)
-    got = C[rows, cols]
-    scaled = float(np.max(np.abs(got - cref) / sref))
-    pure = float(np.max(np.abs(got - cref) / np.abs(cref)))
-    log("max scaled err %.3g, max pure rel err %.3g" % (scaled, pure))
+    flops = 2.0 * n * n * n
 
+    def accuracy():
+        got = dC.cpu().numpy()[rows, cols]
+        return (float(np.max(np.abs(got - cref) / sref)),
+                float(np.max(np.abs(got - cref) / np.abs(cref))))
+
+    paths = {}
+    want = args.paths.split(",")
+    for name in want:
+        prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16, "fp8": hs.SPLIT_FP8}[name]
+        opts = {} if name != "fp8" else {"slices": 7}
+        plan = hs.Plan(n, P, Q, G, b, M, prec=prec, **opts)
+        ws = plan.workspace()
+        run = lambda: plan.run(dA, dB, dC, ws=ws, stream=stream)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = time_region(run, args.steps, stream)
+        wall = time.perf_counter() - t0
+        scaled, pure = accuracy()
+        rec = {"ms_per_step": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+               "wall_s": round(wall, 3), "max_scaled_err": scaled, "max_pure_rel_err": pure,
+               "outer_steps": plan.num_outer_steps, "inner_steps": plan.num_steps}
+        nouter = plan.num_outer_steps
+        if name == "fp64":
+            # one update launch per outer step: 2 n^2 M flops each
+            per_launch = 2.0 * n * n * M
+            avg_ms = ms / nouter
+            ach = per_launch / (avg_ms * 1e-3) / 1e12
+            src = source_hash("k_fp64.hip")
+            rec.update({"fp64_accurate": scaled <= GATE, "dtype": "f64",
+                        "frac_fp64_peak": round(rec["gflops"] / 1e3 / PEAK_FP64, 4)})
+            rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_FP64,
+                               "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64, 4),
+                               "traffic": committed_traffic("fp64_update", wl, src),
+                               "kernel": "fp64_dma_kernel<128,128,2,2,2,2>",
+                               "flops_per_launch": per_launch, "launches_per_step": nouter,
+                               "avg_launch_ms": round(avg_ms, 4), "source_hash": src}
+        else:
+            sl = plan.panel_slices(ws)
+            s = max(sl)
+            pairs = s * (s + 1) // 2
+            # time the product kernel alone on the last split panel
+            C2 = torch.empty_like(dC)
+            last = nouter - 1
+            prod = lambda: plan.outer_products(last, C2, ws, stream=stream)
+            with torch.cuda.stream(stream):
+                prod()
+            torch.cuda.synchronize()
+            pms = time_region(prod, max(3, args.steps), stream)
+            w = n - last * M
+            per_launch = pairs * 2.0 * n * n * w
+            peak = PEAK_BF16 if name == "bf16" else PEAK_FP8
+            ach = per_launch / (pms * 1e-3) / 1e12
+            kern = "slice_bf16_kernel" if name == "bf16" else "slice_update_kernel<fp8>"
+            rec.update({"slices": sorted(set(sl)), "pairs": pairs,
+                        "fp64_accurate": name == "bf16" and scaled <= GATE,
+                        "dtype": "bf16" if name == "bf16" else "fp8-e4m3",
+                        "mfma_util": round(pairs * flops / (ms * 1e-3) / 1e12 / peak, 4)})
+            rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak,
+                               "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                               "traffic": None, "kernel": kern,
+                               "flops_per_launch": per_launch, "launches_per_step": nouter,
+                               "avg_launch_ms": round(pms, 4)}
+        paths[name] = rec
+        log("%s: %.2f ms/step, %.1f GFLOP/s, scaled err %.3g" % (name, ms, rec["gflops"], scaled))
+        del ws, plan
+
+    accurate = {k: v for k, v in paths.items() if v.get("fp64_accurate")}
+    best = max(accurate, key=lambda k: accurate[k]["gflops"]) if accurate else "fp64"
+    head = paths[best]
     out = {
         "metric": "FP64-accurate GFLOP/s at n=16384: split-BF16/FP8 vs FP64-MFMA, % roofline",
-        "value": round(gflops, 1),
+        "value": head["gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": head["dtype"],
         "data": "synthetic",
-        "path": "fp64-mfma",
-        "config": {"workload": "HSUMMA local updates, n=%d, %dx%d grid, G=%d, b=%d, M=%d, "
-                               "U[-1,1] FP64" % (n, P, Q, G, b, M),
-                   "n": n, "P": P, "Q": Q, "G": G, "b": b, "M": M,
-                   "tile": list(tile.values()) if tile else "default"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                     "kernel": "fp64_update_kernel", "launches_per_step": launches,
-                     "flops_per_launch": per_launch_flops},
-        "accuracy": {"max_scaled_err": scaled, "max_pure_rel_err": pure,
-                     "samples": int(rows.size)},
+        "path": {"fp64": "fp64-mfma", "bf16": "split-bf16", "fp8": "split-fp8"}[best],
+        "config": {"workload": "HSUMMA local updates, n=%d FP64, %dx%d grid, G=%d, b=%d, M=%d, "
+                               "entries u*2^rint(N(0,%g)), u~U[-1,1]" % (n, P, Q, G, b, M,
+                                                                           args.sigma ** 2),
+                   "n": n, "P": P, "Q": Q, "G": G, "b": b, "M": M, "sigma": args.sigma},
+        "roofline": head["roofline"],
+        "paths": paths,
+        "accuracy_gate": {"metric": "max |c_hat - c| / (|A||B|)_ij on sampled entries",
+                          "limit": GATE, "samples": int(rows.size), "reference": "Dot2 oracle"},
     }
     if not args.no_cpu:
         log("timing CPU oracle (~%.0f s)" % args.cpu_seconds)

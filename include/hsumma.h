@@ -144,6 +144,15 @@ int hsumma_outer_update(hsumma_plan_t plan, int64_t outer,
                         double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Split forms only: the slice-product launch of outer step g alone, on the
+ * digit planes the workspace holds from a previous call that split that
+ * outer step's panel (C += its product).  Lets a caller time or repeat the
+ * matrix-core part without the split.
+ */
+int hsumma_outer_products(hsumma_plan_t plan, int64_t outer, double* C, int64_t ldc, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
  * The whole product C = A x B: every outer step in order (the first one
  * stores instead of accumulating, so C needs no clearing).  With
  * opts.use_graph the launch sequence is captured once per (pointers, stream)

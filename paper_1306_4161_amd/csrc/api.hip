@@ -224,7 +224,7 @@ int check_operands(hsumma_plan_t p, const double* A, int64_t lda, const double* 
 // the precision form.
 int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
                  double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init, int64_t slot,
-                 void* ws, size_t ws_bytes, hipStream_t stream) {
+                 void* ws, size_t ws_bytes, hipStream_t stream, bool products_only = false) {
   hs::WorkItem* items = nullptr;
   int rc = ensure_device(p, &items);
   if (rc) return rc;
@@ -264,13 +264,14 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   if (((uintptr_t)ws) & 255) return invalid("workspace must be 256-byte aligned");
   uint8_t* w8 = (uint8_t*)ws;
   uint32_t* stats = (uint32_t*)(w8 + p->off_stats) + 2 * slot;
-  hipError_t e = hs::launch_zero_u32(stats, 2, stream);
-  if (e != hipSuccess) {
-    set_error(std::string("stats clear: ") + hipGetErrorString(e));
-    return HSUMMA_ERR_DEVICE;
+  hipError_t e = hipSuccess;
+  if (!products_only) {
+    e = hs::launch_zero_u32(stats, 2, stream);
+    if (e != hipSuccess) {
+      set_error(std::string("stats clear: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
   }
-  const int esz = p->fmt == 0 ? 2 : 1;
-  (void)esz;
   hs::SplitArgs sa;
   sa.A = A; sa.lda = lda; sa.B = B; sa.ldb = ldb;
   sa.m = (int32_t)p->m; sa.n = (int32_t)p->n; sa.k0 = (int32_t)k0; sa.w = (int32_t)(k1 - k0);
@@ -282,10 +283,12 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   sa.digB = w8 + p->off_digB; sa.planeB = (int64_t)p->n * sa.Wp;
   sa.eA = (int32_t*)(w8 + p->off_eA); sa.fB = (int32_t*)(w8 + p->off_fB);
   sa.stats = stats;
-  e = hs::launch_split(sa, stream);
-  if (e != hipSuccess) {
-    set_error(std::string("split launch: ") + hipGetErrorString(e));
-    return HSUMMA_ERR_DEVICE;
+  if (!products_only) {
+    e = hs::launch_split(sa, stream);
+    if (e != hipSuccess) {
+      set_error(std::string("split launch: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
   }
   hs::SliceArgs la;
   la.digA = sa.digA; la.planeA = sa.planeA; la.rowsA = sa.m;
@@ -533,6 +536,19 @@ int hsumma_outer_update(hsumma_plan_t p, int64_t outer, const double* A, int64_t
   if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
   return launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1], 0,
                       outer, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int hsumma_outer_products(hsumma_plan_t p, int64_t outer, double* C, int64_t ldc, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!p) return invalid("null plan");
+  if (p->fmt < 0) {
+    set_error("hsumma_outer_products is for the split forms");
+    return HSUMMA_ERR_UNSUPPORTED;
+  }
+  if (!C || ldc < p->n || (((uintptr_t)C) & 7)) return invalid("bad C");
+  if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
+  return launch_range(p, nullptr, 0, nullptr, 0, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1],
+                      0, outer, ws, ws_bytes, (hipStream_t)stream, true);
 }
 
 int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,

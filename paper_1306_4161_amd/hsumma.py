@@ -21,7 +21,7 @@ EXPORTED = [
     "hsumma_num_steps", "hsumma_num_outer_steps", "hsumma_groups", "hsumma_tile_shape",
     "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
-    "hsumma_split_layout", "hsumma_mfma_exact_probe",
+    "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
     "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
     "hsumma_mlp_adam",
 ]
@@ -80,6 +80,7 @@ def lib():
         L.hsumma_local_update.argtypes = upd
         L.hsumma_outer_update.argtypes = upd
         L.hsumma_run.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        L.hsumma_outer_products.argtypes = [vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
         L.hsumma_panel_slices.argtypes = [vp, vp, P(i32), vp]
         sz = ctypes.c_size_t
         L.hsumma_split_layout.argtypes = [vp, P(sz), P(sz), P(sz), P(sz), P(i32), P(i32)]
@@ -234,6 +235,12 @@ class Plan:
         a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)
         _check(lib().hsumma_outer_update(self._h, g, a, lda, b, ldb, c, ldc, wsp, wsn,
                                          _stream(stream)))
+
+    def outer_products(self, g, C, ws, stream=None):
+        """Split forms: the product launch of outer step g on the planes in ws."""
+        c, ldc = _dev_ptr(C, "C")
+        _check(lib().hsumma_outer_products(self._h, g, c, ldc, ctypes.c_void_p(ws.data_ptr()),
+                                           ws.numel() * ws.element_size(), _stream(stream)))
 
     def run(self, A, B, C, ws=None, stream=None):
         a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)

@@ -1,0 +1,183 @@
+"""Profiling helpers: the launches that hardware counters are taken on, and
+the text summaries made from rocprofv3's CSV output.
+
+    # launches: a 1 GiB device copy (calibration), then outer-step updates
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o f -- \\
+        python3 -m paper_1306_4161_amd.profiling launches --path fp64
+    # summary file read back by bench.py (HBM bytes per launch)
+    python3 -m paper_1306_4161_amd.profiling traffic --fetch OUT/f_counter_collection.csv \\
+        --write OUT2/w_counter_collection.csv --kernel fp64_dma_kernel ...
+    # per-kernel time table from `rocprofv3 --kernel-trace --stats`
+    python3 -m paper_1306_4161_amd.profiling stats OUT/kt_kernel_stats.csv --command "..."
+
+FETCH_SIZE and WRITE_SIZE count L2-to-memory traffic in KiB per dispatch.
+Each is scaled by what it reads for a plain copy of known size (bytes copied
+/ counted bytes), so that the figure is in true bytes.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import collections
+import hashlib
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash(*names) -> str:
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_1306_4161_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def launches(args):
+    import torch
+    from . import hsumma as hs
+    from . import inputs
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    n = args.n
+    if args.sigma > 0:
+        A = inputs.exponent_spread(n, n, inputs.SEED_A, args.sigma)
+        B = inputs.exponent_spread(n, n, inputs.SEED_B, args.sigma)
+    else:
+        A = inputs.uniform(n, n, inputs.SEED_A)
+        B = inputs.uniform(n, n, inputs.SEED_B)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    del A, B
+    dC = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16}[args.path]
+    plan = hs.Plan(n, args.P, args.Q, args.G, args.b, args.M, prec=prec)
+    ws = plan.workspace()
+    for g in range(min(args.count, plan.num_outer_steps)):
+        plan.outer_update(g, dA, dB, dC, ws=ws)
+        torch.cuda.synchronize()
+        print("launch %d done" % g, flush=True)
+
+
+def _per_dispatch(path):
+    """{dispatch id: (kernel name, {counter: summed value})}."""
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            did = int(r["Dispatch_Id"])
+            name, vals = out.setdefault(did, (r["Kernel_Name"], collections.defaultdict(float)))
+            vals[r["Counter_Name"]] += float(r["Counter_Value"])
+    return out
+
+
+def _mean(values):
+    values = list(values)
+    return sum(values) / len(values)
+
+
+def traffic(args):
+    fetch = _per_dispatch(args.fetch)
+    write = _per_dispatch(args.write)
+
+    def pick(table, counter, key):
+        v = [vals[counter] for _, (nm, vals) in sorted(table.items()) if key in nm]
+        if not v:
+            raise SystemExit("no dispatch of %r with %s" % (key, counter))
+        return v
+
+    cf = _mean(pick(fetch, "FETCH_SIZE", COPY_KERNEL))
+    cw = _mean(pick(write, "WRITE_SIZE", COPY_KERNEL))
+    kf = pick(fetch, "FETCH_SIZE", args.kernel)
+    kw = pick(write, "WRITE_SIZE", args.kernel)
+    sf = COPY_BYTES / (cf * 1024.0)
+    sw = COPY_BYTES / (cw * 1024.0)
+    fb = _mean(kf) * 1024.0 * sf
+    wb = _mean(kw) * 1024.0 * sw
+    total = fb + wb
+    lines = [
+        "# HBM traffic per launch of %s, workload %s" % (args.kernel, args.workload),
+        "# fetch command: %s" % args.fetch_command,
+        "# write command: %s" % args.write_command,
+        "# summary command: python3 -m paper_1306_4161_amd.profiling traffic %s" % " ".join(
+            sys.argv[2:]),
+        "# calibration: 1 GiB copy (%s) reads FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB"
+        % (COPY_KERNEL, cf, cw),
+        "kernel: %s" % args.kernel,
+        "source_hash: %s" % source_hash(*args.source.split(",")),
+        "dispatches: %d fetch, %d write" % (len(kf), len(kw)),
+        "fetch_kib_raw_mean: %.1f" % _mean(kf),
+        "write_kib_raw_mean: %.1f" % _mean(kw),
+        "fetch_scale: %.4f" % sf,
+        "write_scale: %.4f" % sw,
+        "fetch_bytes_per_launch: %.6g" % fb,
+        "write_bytes_per_launch: %.6g" % wb,
+        "hbm_bytes_per_launch: %.6g" % total,
+    ]
+    if args.algorithmic:
+        lines.append("algorithmic_bytes_per_launch: %.6g" % args.algorithmic)
+        lines.append("traffic_over_algorithmic: %.3f" % (total / args.algorithmic))
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
+def stats(args):
+    with open(args.csv) as f:
+        rows = list(csv.DictReader(f))
+    lines = ["# per-kernel time, rocprofv3 --kernel-trace --stats",
+             "# command: %s" % args.command,
+             "%-62s %6s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_ms", "pct")]
+    for r in rows[: args.top]:
+        lines.append("%-62s %6s %12.1f %12.2f %7.2f" % (
+            r["Name"][:62], r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("launches")
+    a.add_argument("--path", default="fp64", choices=["fp64", "bf16"])
+    a.add_argument("--n", type=int, default=16384)
+    a.add_argument("--P", type=int, default=16)
+    a.add_argument("--Q", type=int, default=16)
+    a.add_argument("--G", type=int, default=16)
+    a.add_argument("--b", type=int, default=256)
+    a.add_argument("--M", type=int, default=1024)
+    a.add_argument("--sigma", type=float, default=2.0)
+    a.add_argument("--count", type=int, default=3)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--source", required=True, help="comma-separated csrc files")
+    t.add_argument("--algorithmic", type=float, default=0.0)
+    t.add_argument("--fetch-command", default="")
+    t.add_argument("--write-command", default="")
+    t.add_argument("--out", default="")
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--command", default="")
+    s.add_argument("--top", type=int, default=12)
+    s.add_argument("--out", default="")
+    args = ap.parse_args()
+    {"launches": launches, "traffic": traffic, "stats": stats}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()
