@@ -101,14 +101,16 @@ def cpu_baseline(A, B, target_s):
     from oracle import core
     core.build()
     n, k = B.shape[1], A.shape[1]
-    r = 8
-    t0 = time.perf_counter()
-    core.gemm(A[:r], B)
-    dt = time.perf_counter() - t0
-    rows = int(max(r, min(A.shape[0], r * target_s / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    core.gemm(A[:rows], B)
-    dt = time.perf_counter() - t0
+    rows = 8
+    # grow the row count until one run takes at least half the target (the
+    # threaded loop gets faster per row as the slice grows)
+    for attempt in range(4):
+        t0 = time.perf_counter()
+        core.gemm(A[:rows], B)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_s or rows >= A.shape[0] or attempt == 3:
+            break
+        rows = int(max(rows + 1, min(A.shape[0], rows * target_s / max(dt, 1e-6))))
     return {"value": round(2.0 * rows * n * k / dt / 1e9, 3), "unit": "GFLOP/s",
             "cores": core.threads(), "kind": "oracle",
             "sample": "rows 0..%d of C: %d x %d x %d plain FP64 triple loop (%.1f s)" % (
@@ -220,7 +222,10 @@ def main():
                         "mfma_util": round(pairs * flops / (ms * 1e-3) / 1e12 / peak, 4)})
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak,
                                "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                               "traffic": None, "kernel": kern,
+                               "traffic": (committed_traffic("slice_bf16", wl,
+                                                             source_hash("k_split.hip"))
+                                           if name == "bf16" else None),
+                               "kernel": kern,
                                "flops_per_launch": per_launch, "launches_per_step": nouter,
                                "avg_launch_ms": round(pms, 4)}
         paths[name] = rec

@@ -293,6 +293,11 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   hs::SliceArgs la;
   la.digA = sa.digA; la.planeA = sa.planeA; la.rowsA = sa.m;
   la.digB = sa.digB; la.planeB = sa.planeB; la.rowsB = sa.n;
+  {
+    const int64_t esz = p->fmt == 0 ? 2 : 1;
+    la.bytesA = (uint32_t)(p->opts.max_slices * sa.planeA * esz);
+    la.bytesB = (uint32_t)(p->opts.max_slices * sa.planeB * esz);
+  }
   la.eA = sa.eA; la.fB = sa.fB; la.stats = stats;
   la.slices_out = (int32_t*)(w8 + p->off_slices) + slot;
   la.C = C; la.ldc = ldc;
@@ -410,6 +415,13 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     const int64_t Wp = (M + pad - 1) / pad * pad;
     p->Wp = (int32_t)Wp;
     const int64_t esz = p->fmt == 0 ? 2 : 1;
+    // the slice kernels address each operand's digit planes through a buffer
+    // descriptor with 32-bit offsets
+    if (p->opts.max_slices * std::max(m, n) * Wp * esz > (int64_t)0xFFFFFFFF) {
+      delete p;
+      return invalid("split form: the digit planes of one operand panel exceed 4 GiB "
+                     "(max_slices x rows x padded M x digit bytes); use a smaller outer block M");
+    }
     const int64_t nout = (k + M - 1) / M;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;

@@ -32,6 +32,17 @@ struct UpdateArgs {
   int32_t persistent;  // 1: grid-stride over the items (grouped persistent mode)
 };
 
+// Workgroup barrier of an LDS ring filled by direct-to-LDS loads.  Each wave
+// first waits (s_waitcnt vmcnt) for its own loads of the stage it is about to
+// read; __syncthreads() would add a release fence, i.e. a wait for every
+// outstanding load, including those of later stages that are meant to stay in
+// flight across the barrier.  lgkmcnt(0) retires this wave's LDS reads of the
+// stage that is refilled next; the "memory" clobber keeps the compiler from
+// moving LDS accesses across the barrier.
+__device__ __forceinline__ void ring_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Kernel configurations (macro-tile and k-chunk) compiled into the library.
 struct TileCfg { int tm, tn, kc; };
 const std::vector<TileCfg>& fp64_configs();

@@ -356,7 +356,7 @@ void fp64_dma_kernel(UpdateArgs p) {
         asm volatile("s_waitcnt vmcnt(%0)" ::"n"(AINS + BINS) : "memory");
       else
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
+      ring_barrier();
       // refill the stage consumed in the previous iteration
       if (ci + NS - 1 < nchunks) {
         int c0, clen;

@@ -479,28 +479,42 @@ void slice_update_kernel(SliceArgs p) {
 }
 
 // ---- BF16 slice products, streamed ------------------------------------------
-// Workgroup tile 64 x 128, 8 waves (2 x 4) of one 32x32 block each, on
+// Workgroup tile 64 x 128, 4 waves (2 x 2, one per SIMD) of a 32 x 64 block
+// each (two 32x32 blocks sharing the A fragment), on
 // v_mfma_f32_32x32x16_bf16.  Per 16-k step the digits of every plane of the
 // tile stream from global memory straight into an NS-stage LDS ring
-// (global_load_lds_dwordx4; 6 x SMAX wave-instructions per step spread over
-// the 8 waves).  LDS image of one plane: [row][half] 16-byte units, the half
-// index XOR-swizzled by bit 3 of the row so that a fragment read (32 rows x
-// one half) is bank-conflict free.
+// (global_load_lds_dwordx4, 6 S wave-instructions per step over the 4 waves).
+// LDS image of one plane: [row][half] 16-byte units, the half index
+// XOR-swizzled by bit 3 of the row so that a fragment read (32 rows x one
+// half) is bank-conflict free.
 //
 // 32x32x16 operand layout: lane l holds A[l % 32][8 (l / 32) .. + 7] and
 // B[8 (l / 32) .. + 7][l % 32]; D item v of lane l is
 // D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
 //
+// Pairs (l1, l2), l1 + l2 < S, run in S rows; row r pairs A fragment
+// S-1-r with B fragments 0 .. r, so every row needs one new fragment of each
+// operand.  Fragment reads run three rows ahead of the MFMAs (one wave per
+// SIMD has no other wave to hide LDS latency behind).  The step's one
+// barrier sits three rows before its end: every read of the current stage
+// has retired, so the stage is refilled by DMA for the step NS ahead (each
+// load has NS - 1 steps to land), and the next stage is complete, so its
+// first rows are read into the second register set while the step ends.
+//
 // Level accumulators (FP32): index a = l1 + l2 (0-based) for a <= 3, one
 // shared accumulator for a >= 4.  Exact while a level's partial sums stay
-// within 2^24: a level of a + 1 pairs of |d d'| <= 2^16 may run 256/(a+1) k,
-// so levels 0, 1, 2-3 are added into the FP64 panel sum every 256, 128, 64 k
-// (the panel is padded to a multiple of 64); the shared deep accumulator
-// (weight <= 2^-36) needs no exactness and is added every 256 k.
+// within 2^24: a level of a + 1 pairs of |d d'| <= 2^16 may run 256/(a+1) k.
+// Every accumulator is added into the FP64 panel sum after each group of
+// four steps (64 k; the panel is padded to a multiple of 64) and restarts
+// from a zero C operand, so levels 0-3 stay exact; the shared deep
+// accumulator (weight <= 2^-36) needs no exactness.
 //
 // The slice count S is a template parameter of the item loop (the kernel
 // dispatches on the panel's count once), so the pair structure is static.
-constexpr int kBf16TM = 64, kBf16TN = 128, kBf16NW = 8;
+constexpr int kBf16TM = 64, kBf16TN = 128, kBf16NW = 4;
+// Buffer descriptor word 3 for raw (untyped) buffer loads on CDNA: data
+// format 32 bits, no swizzle, no index stride.
+constexpr int kBufferWord3 = 0x00020000;
 constexpr int kBf16Lds = 152 * 1024;  // LDS ring budget (bytes)
 // ring depth for S planes: as many 16-k stages as fit, at most 5
 constexpr int bf16_stages(int S) {
@@ -508,29 +522,43 @@ constexpr int bf16_stages(int S) {
                                                           : 5;
 }
 
+// Wait until at most k x PER of this wave's vector-memory instructions are
+// outstanding (k <= KMAX, known only at run time; the count is an immediate).
+template <int PER, int KMAX>
+__device__ __forceinline__ void vm_wait_steps(int k) {
+  if (KMAX >= 4 && k >= 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(4 * PER) : "memory");
+  else if (KMAX >= 3 && k == 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * PER) : "memory");
+  else if (KMAX >= 2 && k == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * PER) : "memory");
+  else if (KMAX >= 1 && k == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PER) : "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 template <int S>
 __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* smem) {
-  constexpr int SMAX = kSplitMaxSlices;        // planes present in the workspace
   constexpr int TM = kBf16TM, TN = kBf16TN, NW = kBf16NW, NS = bf16_stages(S);
   constexpr int ABYTES = S * TM * 32, BBYTES = S * TN * 32, SB = ABYTES + BBYTES;
-  constexpr int NI = 6 * S;                    // DMA wave-instructions per 16-k step
-  constexpr int NIHI = (NI + NW - 1) / NW, NILO = NI / NW;
+  // DMA wave-instructions per 16-k step of waves 0-1 and 2-3
+  constexpr int NIHI = 3 * (S / 2) + (S & 1 ? 2 : 0), NILO = 3 * (S / 2) + (S & 1);
   constexpr int NACC = S < 5 ? S : 5;
-  static_assert(NS >= 3 && NS * (S * (TM + TN) * 32) <= kBf16Lds, "LDS ring");
-  (void)SMAX;
+  constexpr int LAG = S < 3 ? S : 3;           // rows of fragment reads ahead of the MFMAs
+  static_assert(NS >= 3 && NS * SB <= kBf16Lds, "LDS ring");
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 2, wn = wave & 3;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+  const int wm = wave >> 1, wn = wave & 1;
   const int l32 = lane & 31, lh = lane >> 5;
-  const int my_ni = (NI - wave + NW - 1) / NW;  // this wave's DMA instructions per step
+  const bool hi = wave < 2;                     // this wave issues NIHI per step
 
-  const uint8_t* gA = (const uint8_t*)p.digA;
-  const uint8_t* gB = (const uint8_t*)p.digB;
-  const int64_t kbA = (int64_t)p.rowsA * 32, kbB = (int64_t)p.rowsB * 32;  // bytes per k16 block
-  const int nsteps = p.Wp / 16;
+  const __amdgpu_buffer_rsrc_t rsrcA =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.digA, (short)0, (int)p.bytesA, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rsrcB =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.digB, (short)0, (int)p.bytesB, kBufferWord3);
+  const uint32_t kbA = (uint32_t)p.rowsA * 32u, kbB = (uint32_t)p.rowsB * 32u;  // bytes per k16 block
+  const uint32_t planeAB = (uint32_t)(p.planeA * 2), planeBB = (uint32_t)(p.planeB * 2);
+  const int nsteps = p.Wp / 16;                // a multiple of 4
   const int arow = wm * 32 + l32;
   const int aoff = (arow * 2 + (lh ^ ((arow >> 3) & 1))) * 16;
-  const int bcol = wn * 32 + l32;
+  const int bcol = wn * 64 + l32;              // block 1 is 32 columns on: same swizzle bit
   const int boff = (bcol * 2 + (lh ^ ((bcol >> 3) & 1))) * 16;
 
   const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
@@ -543,147 +571,171 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
     if (idx >= p.nitems) break;
     const WorkItem it = p.items[idx];
 
-    // This wave's DMA sources for k16 block 0 (per-item constants); block kb
-    // adds kb x (rows x 32 bytes).  LDS destinations are uniform.
-    const uint8_t* src0[NIHI];
-    int64_t kstride[NIHI];
-    int dst_off[NIHI];
+    // DMA: a 16-k step moves, per plane, 2 wave-instructions of A (64 rows x
+    // 32 bytes) and 4 of B (128 columns x 32 bytes), 64 16-byte units each
+    // (unit u = row or column u/2, half u%2).  Per pair of planes (l, l+1)
+    // wave w loads A half w%2 of plane l + w/2 and B quarter w of both
+    // planes; an odd last plane gives its A halves to waves 0, 1.  So each
+    // wave has one per-lane byte offset into A and one into B (ragged rows
+    // and columns clamped to the last valid one); plane and k16 block are a
+    // uniform offset in the buffer descriptor's soffset.
+    const int ua = (wave & 1) * 64 + lane;
+    const int rowa = ua >> 1, halfa = (ua & 1) ^ ((rowa >> 3) & 1);
+    const uint32_t voffA = (uint32_t)(it.r0 + min(rowa, it.h - 1)) * 32u + halfa * 16u;
+    const int ub = wave * 64 + lane;
+    const int colb = ub >> 1, halfb = (ub & 1) ^ ((colb >> 3) & 1);
+    const uint32_t voffB = (uint32_t)(it.c0 + min(colb, it.w - 1)) * 32u + halfb * 16u;
+    // row of this lane's D item v in the item; exponents of the lane's 16
+    // rows and 2 columns (clamped into the item), fetched before the k loop
+    auto erow = [&](int v) { return wm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3); };
+    int ea[16];
 #pragma unroll
-    for (int j = 0; j < NIHI; ++j) {
-      const int t = min(wave + NW * j, NI - 1);
-      if (t < 2 * S) {
-        const int plane = t >> 1, u = (t & 1) * 64 + lane;
-        const int row = u >> 1, half = (u & 1) ^ ((row >> 3) & 1);
-        const int grow = it.r0 + min(row, it.h - 1);
-        src0[j] = gA + plane * p.planeA * 2 + (int64_t)grow * 32 + half * 16;
-        kstride[j] = kbA;
-        dst_off[j] = plane * (TM * 32) + (t & 1) * 1024;
-      } else {
-        const int tb = t - 2 * S;
-        const int plane = tb >> 2, u = (tb & 3) * 64 + lane;
-        const int col = u >> 1, half = (u & 1) ^ ((col >> 3) & 1);
-        const int gcol = it.c0 + min(col, it.w - 1);
-        src0[j] = gB + plane * p.planeB * 2 + (int64_t)gcol * 32 + half * 16;
-        kstride[j] = kbB;
-        dst_off[j] = ABYTES + plane * (TN * 32) + (tb & 3) * 1024;
-      }
-    }
+    for (int v = 0; v < 16; ++v) ea[v] = p.eA[it.r0 + min(erow(v), it.h - 1)];
+    const int fb0c = p.fB[it.c0 + min(wn * 64 + l32, it.w - 1)];
+    const int fb1c = p.fB[it.c0 + min(wn * 64 + 32 + l32, it.w - 1)];
+    auto dmaA = [&](int plane, int kb, uint8_t* dst) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsrcA, (__attribute__((address_space(3))) void*)dst, 16, voffA,
+          (uint32_t)(plane * planeAB + kb * kbA), 0, 0);
+    };
+    auto dmaB = [&](int plane, int kb, uint8_t* dst) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsrcB, (__attribute__((address_space(3))) void*)dst, 16, voffB,
+          (uint32_t)(plane * planeBB + kb * kbB), 0, 0);
+    };
     auto issue = [&](int kb, int st) {
       uint8_t* stage = smem + st * SB;
 #pragma unroll
-      for (int j = 0; j < NIHI; ++j) {
-        if (wave + NW * j < NI)
-          __builtin_amdgcn_global_load_lds(src0[j] + kb * kstride[j],
-                                           (__attribute__((address_space(3))) void*)(stage + dst_off[j]),
-                                           16, 0, 0);
+      for (int l = 0; l + 1 < S; l += 2) {
+        const int pa = l + (wave >> 1);
+        dmaA(pa, kb, stage + pa * (TM * 32) + (wave & 1) * 1024);
+        dmaB(l, kb, stage + ABYTES + l * (TN * 32) + wave * 1024);
+        dmaB(l + 1, kb, stage + ABYTES + (l + 1) * (TN * 32) + wave * 1024);
+      }
+      if (S & 1) {
+        if (wave < 2) dmaA(S - 1, kb, stage + (S - 1) * (TM * 32) + wave * 1024);
+        dmaB(S - 1, kb, stage + ABYTES + (S - 1) * (TN * 32) + wave * 1024);
+      }
+    };
+    // wait for this wave's loads of step s, with `later` steps issued after it
+    auto wait_step = [&](int later) {
+      if (hi) vm_wait_steps<NIHI, NS - 1>(later);
+      else vm_wait_steps<NILO, NS - 1>(later);
+    };
+
+    f16v acc0[NACC], acc1[NACC];               // level accumulators, blocks 0 and 1
+    double cp0[16], cp1[16];                   // FP64 panel sums
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      cp0[v] = 0.0;
+      cp1[v] = 0.0;
+    }
+
+    // Fragments.  Rows run in the order r = 0 .. S-1, row r pairing A
+    // fragment S-1-r with B fragments 0 .. r, so each row needs one new A and
+    // one new B fragment (per block).  Reads run LAG rows ahead of the MFMAs;
+    // the last LAG rows of a step read the first LAG rows of the next step
+    // into the other register set.
+    bf8v fa[2][S], fb0[2][S], fb1[2][S];
+    auto read_row = [&](int set, int st, int r) {
+      const uint8_t* sA = smem + st * SB;
+      const uint8_t* sB = sA + ABYTES;
+      fa[set][S - 1 - r] = *(const bf8v*)(sA + (S - 1 - r) * (TM * 32) + aoff);
+      fb0[set][r] = *(const bf8v*)(sB + r * (TN * 32) + boff);
+      fb1[set][r] = *(const bf8v*)(sB + r * (TN * 32) + boff + 1024);
+    };
+    // In the first step of a group of four every accumulator starts from
+    // zero: its first pair (row S-1-a, or row 0 for the shared deep one, with
+    // l2 = 0) takes a zero C operand.
+    const f16v zero = {};
+    auto row = [&](int set, int r, bool first) {
+      const int l1 = S - 1 - r;
+#pragma unroll
+      for (int l2 = 0; l2 <= r; ++l2) {
+        const int a = (l1 + l2) < NACC - 1 ? (l1 + l2) : NACC - 1;
+        const bool z = first && l2 == 0 && r == (a == NACC - 1 ? 0 : S - 1 - a);
+        acc0[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[set][l1], fb0[set][l2], z ? zero : acc0[a],
+                                                          0, 0, 0);
+        acc1[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[set][l1], fb1[set][l2], z ? zero : acc1[a],
+                                                          0, 0, 0);
+      }
+    };
+    // every accumulator is added into the FP64 panel sum after each group of
+    // four steps (64 k), within the exactness bound of every level
+    auto flush = [&]() {
+#pragma unroll
+      for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          cp0[v] += (double)acc0[a][v];
+          cp1[v] += (double)acc1[a][v];
+        }
+    };
+    // one 16-k step: fragments of step ci are in set `cur`.  The barrier sits
+    // before row S-LAG: by then every fragment of step ci has been read
+    // (ring_barrier retires the reads), so stage ci is free for the DMA of
+    // step ci+NS, and stage ci+1 is complete for every wave.
+    auto step = [&](int ci, int cur, bool first) {
+      const int nxt = cur ^ 1;
+      const bool more = ci + 1 < nsteps;
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        if (r == S - LAG && more) {
+          wait_step(min(NS - 2, nsteps - 2 - ci));   // step ci + 1 landed (this wave)
+          ring_barrier();
+          if (ci + NS < nsteps) issue(ci + NS, ci % NS);
+        }
+        if (r + LAG < S) read_row(cur, ci % NS, r + LAG);
+        else if (more) read_row(nxt, (ci + 1) % NS, r + LAG - S);
+        row(cur, r, first);
+        __builtin_amdgcn_sched_barrier(0);
       }
     };
 
-    f16v acc[NACC];
-    double cp[16];
+    // prologue: NS steps in flight, then the first LAG rows of step 0
 #pragma unroll
-    for (int a = 0; a < NACC; ++a)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[a][v] = 0.f;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) cp[v] = 0.0;
-
-#pragma unroll
-    for (int st = 0; st < NS - 1; ++st)
+    for (int st = 0; st < NS; ++st)
       if (st < nsteps) issue(st, st);
+    wait_step(min(NS - 1, nsteps - 1));
+    ring_barrier();
+#pragma unroll
+    for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
 
-    // Levels are added into the FP64 panel sum at their exactness cadence
-    // (period in 16-k steps): a = 0 every 16, a = 1 every 8, a = 2, 3 every
-    // 4, the shared deep accumulator every 16.
-    constexpr int PER[5] = {16, 8, 4, 4, 16};
-    for (int ci = 0; ci < nsteps; ++ci) {
-      const int ahead = min(NS - 2, nsteps - 1 - ci);
-      // wait for this wave's loads of step ci (later steps stay in flight)
-      // (vmcnt counts this wave's DMA instructions in issue order; `ahead`
-      // later steps of my_ni instructions each may stay outstanding)
-      if (my_ni == NIHI) {
-        if (ahead >= 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * NIHI) : "memory");
-        else if (ahead == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * NIHI) : "memory");
-        else if (ahead == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NIHI) : "memory");
-        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      } else {
-        if (ahead >= 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * NILO) : "memory");
-        else if (ahead == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * NILO) : "memory");
-        else if (ahead == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NILO) : "memory");
-        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      }
-      __syncthreads();
-      if (ci + NS - 1 < nsteps) issue(ci + NS - 1, (ci + NS - 1) % NS);
-
-      const uint8_t* sA = smem + (ci % NS) * SB;
-      const uint8_t* sB = sA + ABYTES;
-      constexpr int last_acc = NACC - 1;
-      if (S <= 6) {
-        // fragments are read in the order A0, B0, A1, B1, ... and the pairs
-        // run level by level, so each level needs one new A and one new B
-        // fragment and the LDS latency hides behind the earlier levels
-        bf8v afr[S], bfr[S];
-#pragma unroll
-        for (int l = 0; l < S; ++l) {
-          afr[l] = *(const bf8v*)(sA + l * (TM * 32) + aoff);
-          bfr[l] = *(const bf8v*)(sB + l * (TN * 32) + boff);
-        }
-#pragma unroll
-        for (int L = 0; L < S; ++L) {
-#pragma unroll
-          for (int l1 = 0; l1 <= L; ++l1) {
-            const int a = L < last_acc ? L : last_acc;
-            acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[l1], bfr[L - l1], acc[a], 0, 0, 0);
-          }
-        }
-      } else {
-        // seven planes: keep every B fragment, stream the A fragments (fewer
-        // live registers)
-        bf8v bfr[S];
-#pragma unroll
-        for (int l2 = 0; l2 < S; ++l2) bfr[l2] = *(const bf8v*)(sB + l2 * (TN * 32) + boff);
-#pragma unroll
-        for (int l1 = 0; l1 < S; ++l1) {
-          const bf8v afr = *(const bf8v*)(sA + l1 * (TM * 32) + aoff);
-#pragma unroll
-          for (int l2 = 0; l2 < S - l1; ++l2) {
-            const int a = (l1 + l2) < last_acc ? (l1 + l2) : last_acc;
-            acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[l2], acc[a], 0, 0, 0);
-          }
-        }
-      }
-      const bool last = ci + 1 == nsteps;
-      const int nxt = ci + 1;
-#pragma unroll
-      for (int a = NACC - 1; a >= 0; --a) {
-        const int per = PER[a < 4 ? a : 4];
-        if (last || (nxt % per) == 0) {
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            cp[v] += (double)acc[a][v];
-            acc[a][v] = 0.f;
-          }
-        }
-      }
+    for (int ci = 0; ci < nsteps; ci += 4) {
+      step(ci, 0, true);
+      step(ci + 1, 1, false);
+      step(ci + 2, 0, false);
+      step(ci + 3, 1, false);
+      flush();
     }
     __syncthreads();  // the ring is reused by the next item
 
-    // C += 2^(e_i + f_j - 16) x panel sum
-    const int col = wn * 32 + l32;
+    // C += 2^(e_i + f_j - 16) x panel sum.  Addresses are clamped into the
+    // item so that every load is unconditional (all in flight at once); only
+    // the stores are predicated.
+    double cold0[16], cold1[16];
+    if (!p.zero_init) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const double* crow = p.C + (int64_t)(it.r0 + min(erow(v), it.h - 1)) * p.ldc + it.c0;
+        cold0[v] = crow[min(wn * 64 + l32, it.w - 1)];
+        cold1[v] = crow[min(wn * 64 + 32 + l32, it.w - 1)];
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int row = wm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3);
-      if (row < it.h && col < it.w) {
-        const int gr = it.r0 + row, gc = it.c0 + col;
-        const double add = ldexp(cp[v], p.eA[gr] + p.fB[gc] - 16);
-        double* cptr = p.C + (int64_t)gr * p.ldc + gc;
-        *cptr = p.zero_init ? add : *cptr + add;
-      }
+      const int row = erow(v);
+      double* crow = p.C + (int64_t)(it.r0 + row) * p.ldc + it.c0;
+      const int col0 = wn * 64 + l32, col1 = col0 + 32;
+      const double add0 = ldexp(cp0[v], ea[v] + fb0c - 16);
+      const double add1 = ldexp(cp1[v], ea[v] + fb1c - 16);
+      if (row < it.h && col0 < it.w) crow[col0] = p.zero_init ? add0 : cold0[v] + add0;
+      if (row < it.h && col1 < it.w) crow[col1] = p.zero_init ? add1 : cold1[v] + add1;
     }
   }
 }
 
-__global__ __launch_bounds__(512, 1) void slice_bf16_kernel(SliceArgs p) {
+__global__ __launch_bounds__(256, 1) void slice_bf16_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
   int s = p.fixed_s;
   if (s <= 0) {
@@ -770,7 +822,7 @@ hipError_t launch_zero_u32(uint32_t* ptr, int n, hipStream_t s) {
 
 hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s) {
   if (fmt == 0)
-    hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(512), 0, s, a);
+    hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((slice_update_kernel<1, kSplitMaxSlices, 2, 2>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -23,6 +23,7 @@ struct SplitArgs {
 struct SliceArgs {
   const void* digA; int64_t planeA; int32_t rowsA;   // rowsA = m
   const void* digB; int64_t planeB; int32_t rowsB;   // rowsB = n
+  uint32_t bytesA, bytesB;           // byte sizes of the two digit regions (< 4 GiB)
   const int32_t* eA; const int32_t* fB;
   const uint32_t* stats; int32_t* slices_out;
   double* C; int64_t ldc;

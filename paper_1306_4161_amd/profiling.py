@@ -21,6 +21,7 @@ import csv
 import collections
 import hashlib
 import os
+import shlex
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -105,8 +106,8 @@ def traffic(args):
         "# HBM traffic per launch of %s, workload %s" % (args.kernel, args.workload),
         "# fetch command: %s" % args.fetch_command,
         "# write command: %s" % args.write_command,
-        "# summary command: python3 -m paper_1306_4161_amd.profiling traffic %s" % " ".join(
-            sys.argv[2:]),
+        "# summary command: python3 -m paper_1306_4161_amd.profiling %s" % shlex.join(
+            sys.argv[1:]),
         "# calibration: 1 GiB copy (%s) reads FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB"
         % (COPY_KERNEL, cf, cw),
         "kernel: %s" % args.kernel,
