@@ -190,7 +190,7 @@ def main():
             per_launch = 2.0 * n * n * M
             avg_ms = ms / nouter
             ach = per_launch / (avg_ms * 1e-3) / 1e12
-            src = source_hash("k_fp64.hip", "internal.h")
+            src = source_hash("k_fp64.hip", "internal.h", "api.hip")
             rec.update({"fp64_accurate": scaled <= GATE, "dtype": "f64",
                         "frac_fp64_peak": round(rec["gflops"] / 1e3 / PEAK_FP64, 4)})
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_FP64,
@@ -223,7 +223,7 @@ def main():
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak,
                                "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                                "traffic": (committed_traffic("slice_bf16", wl,
-                                                             source_hash("k_split.hip", "split.h", "internal.h"))
+                                                             source_hash("k_split.hip", "split.h", "internal.h", "api.hip"))
                                            if name == "bf16" else None),
                                "kernel": kern,
                                "flops_per_launch": per_launch, "launches_per_step": nouter,

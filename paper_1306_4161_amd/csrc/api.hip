@@ -8,6 +8,7 @@
 // into 8 contiguous parts, one per XCD: the processors of a group share an
 // L2, the GPU's image of the paper's group-level broadcast.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -152,16 +153,29 @@ void build_items(hsumma_plan_s& p) {
     for (auto& run : runs_of(p, false, c))
       for (int64_t g = run.g0; g < run.g1; g += p.cfg.tn)
         cpieces[c].push_back({g, std::min(g + p.cfg.tn, run.g1)});
+  // Inside a tile the macro-tiles go in blocks of br x bc, sized so that the
+  // workgroups one XCD runs at a time (32 CUs x occupancy) cover a square
+  // of C: they then share the fewest A rows plus B columns per k-slice in
+  // that XCD's L2.
+  const int conc = 32 * (p.fmt < 0 ? std::max(1, hs::fp64_occupancy(p.cfg)) : 1);
+  int bc = std::max(1, (int)std::lround(std::sqrt((double)conc * p.cfg.tm / p.cfg.tn)));
+  int br = std::max(1, conc / bc);
   p.items.clear();
   for (int x = 0; x < p.I; ++x)
     for (int y = 0; y < p.J; ++y)
       for (int i = 0; i < gp; ++i)
         for (int j = 0; j < gq; ++j) {
           const int pr = x * gp + i, pc = y * gq + j;
-          for (auto& rp : rpieces[pr])
-            for (auto& cp : cpieces[pc])
-              p.items.push_back({(int32_t)rp.g0, (int32_t)cp.g0, (int32_t)(rp.g1 - rp.g0),
-                                 (int32_t)(cp.g1 - cp.g0)});
+          const size_t nr = rpieces[pr].size(), nc = cpieces[pc].size();
+          for (size_t rb = 0; rb < nr; rb += br)
+            for (size_t cb = 0; cb < nc; cb += bc)
+              for (size_t ri = rb; ri < std::min(nr, rb + br); ++ri)
+                for (size_t ci = cb; ci < std::min(nc, cb + bc); ++ci) {
+                  const Run& rp = rpieces[pr][ri];
+                  const Run& cp = cpieces[pc][ci];
+                  p.items.push_back({(int32_t)rp.g0, (int32_t)cp.g0, (int32_t)(rp.g1 - rp.g0),
+                                     (int32_t)(cp.g1 - cp.g0)});
+                }
         }
   const int64_t nit = (int64_t)p.items.size();
   p.per_xcd = (int32_t)((nit + 7) / 8);
