@@ -13,9 +13,11 @@ e = rint(N(0, sigma^2 = 4)) (seeded, synthetic).
 
 Paths timed: FP64-MFMA, and the BF16 digit split (slice count chosen per
 panel) -- both FP64-accurate (checked on sampled entries against the Dot2
-oracle: max |c_hat - c| / (|A||B|)_ij <= 1e-14) -- and the FP8-e4m3 split
-(reported, not FP64-accurate).  `value` is the FP64-accurate GFLOP/s
-(2 n^3 / t) of the fastest accurate path; `paths` holds every path.
+oracle: max |c_hat - c| / (|A||B|)_ij <= 1e-14) -- the FP8-e4m3 split
+(reported, not FP64-accurate), and the BF16 split once more on entries
+u ~ U[-1, 1] (`bf16_uniform`: fewer slices suffice there).  `value` is the
+FP64-accurate GFLOP/s (2 n^3 / t) of the fastest accurate path on the
+workload's own entries; `paths` holds every path.
 
 `roofline` describes the dominant kernel of the reported path: its
 algorithmic flops per launch over its average launch duration, measured with
@@ -61,7 +63,7 @@ def parse():
     ap.add_argument("--b", type=int, default=256)
     ap.add_argument("--M", type=int, default=1024)
     ap.add_argument("--sigma", type=float, default=2.0)
-    ap.add_argument("--paths", type=str, default="fp64,bf16,fp8")
+    ap.add_argument("--paths", type=str, default="fp64,bf16,fp8,bf16_uniform")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--samples", type=int, default=512)
@@ -145,22 +147,31 @@ def main():
 
     n, P, Q, G, b, M = args.n, args.P, args.Q, args.G, args.b, args.M
     wl = "n%d" % n
-    log("generating operands n=%d sigma=%g" % (n, args.sigma))
-    if args.sigma > 0:
-        A = inputs.exponent_spread(n, n, inputs.SEED_A, args.sigma)
-        B = inputs.exponent_spread(n, n, inputs.SEED_B, args.sigma)
-    else:
-        A = inputs.uniform(n, n, inputs.SEED_A)
-        B = inputs.uniform(n, n, inputs.SEED_B)
-    dA = torch.from_numpy(A).cuda()
-    dB = torch.from_numpy(B).cuda()
+    rows, cols = inputs.sample_entries(n, n, args.samples, inputs.SEED_SAMPLE)
+    operand_sets = {}
+
+    def operands(sigma):
+        """Host and device operands of one value distribution, with the
+        oracle's values at the sampled entries."""
+        if sigma not in operand_sets:
+            log("generating operands n=%d sigma=%g" % (n, sigma))
+            if sigma > 0:
+                A = inputs.exponent_spread(n, n, inputs.SEED_A, sigma)
+                B = inputs.exponent_spread(n, n, inputs.SEED_B, sigma)
+            else:
+                A = inputs.uniform(n, n, inputs.SEED_A)
+                B = inputs.uniform(n, n, inputs.SEED_B)
+            cref, sref = core.sampled(A, B, rows, cols)
+            operand_sets[sigma] = (A, B, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                                   cref, sref)
+        return operand_sets[sigma]
+
+    A, B, dA, dB, cref, sref = operands(args.sigma)
     dC = torch.empty((n, n), dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
-    rows, cols = inputs.sample_entries(n, n, args.samples, inputs.SEED_SAMPLE)
-    cref, sref = core.sampled(A, B, rows, cols)
     flops = 2.0 * n * n * n
 
-    def accuracy():
+    def accuracy(cref, sref):
         got = dC.cpu().numpy()[rows, cols]
         return (float(np.max(np.abs(got - cref) / sref)),
                 float(np.max(np.abs(got - cref) / np.abs(cref))))
@@ -168,11 +179,15 @@ def main():
     paths = {}
     want = args.paths.split(",")
     for name in want:
-        prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16, "fp8": hs.SPLIT_FP8}[name]
-        opts = {} if name != "fp8" else {"slices": 7}
+        # "<path>_uniform": the same path on entries u ~ U[-1, 1] (sigma = 0)
+        base = name.split("_")[0]
+        sigma = 0.0 if name.endswith("_uniform") else args.sigma
+        _, _, pA, pB, pcref, psref = operands(sigma)
+        prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16, "fp8": hs.SPLIT_FP8}[base]
+        opts = {} if base != "fp8" else {"slices": 7}
         plan = hs.Plan(n, P, Q, G, b, M, prec=prec, **opts)
         ws = plan.workspace()
-        run = lambda: plan.run(dA, dB, dC, ws=ws, stream=stream)
+        run = lambda: plan.run(pA, pB, dC, ws=ws, stream=stream)
         with torch.cuda.stream(stream):
             for _ in range(args.warmup):
                 run()
@@ -180,12 +195,13 @@ def main():
         t0 = time.perf_counter()
         ms = time_region(run, args.steps, stream)
         wall = time.perf_counter() - t0
-        scaled, pure = accuracy()
+        scaled, pure = accuracy(pcref, psref)
         rec = {"ms_per_step": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+               "sigma": sigma,
                "wall_s": round(wall, 3), "max_scaled_err": scaled, "max_pure_rel_err": pure,
                "outer_steps": plan.num_outer_steps, "inner_steps": plan.num_steps}
         nouter = plan.num_outer_steps
-        if name == "fp64":
+        if base == "fp64":
             # one update launch per outer step: 2 n^2 M flops each
             per_launch = 2.0 * n * n * M
             avg_ms = ms / nouter
@@ -213,12 +229,12 @@ def main():
             pms = time_region(prod, max(3, args.steps), stream)
             w = n - last * M
             per_launch = pairs * 2.0 * n * n * w
-            peak = PEAK_BF16 if name == "bf16" else PEAK_FP8
+            peak = PEAK_BF16 if base == "bf16" else PEAK_FP8
             ach = per_launch / (pms * 1e-3) / 1e12
-            kern = "slice_bf16_kernel" if name == "bf16" else "slice_update_kernel<fp8>"
+            kern = "slice_bf16_kernel" if base == "bf16" else "slice_update_kernel<fp8>"
             rec.update({"slices": sorted(set(sl)), "pairs": pairs,
-                        "fp64_accurate": name == "bf16" and scaled <= GATE,
-                        "dtype": "bf16" if name == "bf16" else "fp8-e4m3",
+                        "fp64_accurate": base == "bf16" and scaled <= GATE,
+                        "dtype": "bf16" if base == "bf16" else "fp8-e4m3",
                         "mfma_util": round(pairs * flops / (ms * 1e-3) / 1e12 / peak, 4)})
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak,
                                "unit": "TFLOP/s", "frac": round(ach / peak, 4),
@@ -232,7 +248,9 @@ def main():
         log("%s: %.2f ms/step, %.1f GFLOP/s, scaled err %.3g" % (name, ms, rec["gflops"], scaled))
         del ws, plan
 
-    accurate = {k: v for k, v in paths.items() if v.get("fp64_accurate")}
+    # the headline compares paths on the workload's own value distribution
+    accurate = {k: v for k, v in paths.items()
+                if v.get("fp64_accurate") and v["sigma"] == args.sigma}
     best = max(accurate, key=lambda k: accurate[k]["gflops"]) if accurate else "fp64"
     head = paths[best]
     out = {
@@ -248,7 +266,7 @@ def main():
         "vs_baseline": None,
         "dtype": head["dtype"],
         "data": "synthetic",
-        "path": {"fp64": "fp64-mfma", "bf16": "split-bf16", "fp8": "split-fp8"}[best],
+        "path": {"fp64": "fp64-mfma", "bf16": "split-bf16", "fp8": "split-fp8"}[best.split("_")[0]],
         "config": {"workload": "HSUMMA local updates, n=%d FP64, %dx%d grid, G=%d, b=%d, M=%d, "
                                "entries u*2^rint(N(0,%g)), u~U[-1,1]" % (n, P, Q, G, b, M,
                                                                            args.sigma ** 2),

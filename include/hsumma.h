@@ -83,8 +83,10 @@ typedef struct {
   int32_t kc;         /* k-chunk staged per LDS buffer; 0 => default            */
   int32_t persistent; /* 1: one grouped persistent launch per step              */
   int32_t use_graph;  /* 1: hsumma_run replays a captured HIP graph             */
-  int32_t tau_bits;   /* split forms, per-panel slice choice: target bits of    */
-                      /* accuracy relative to (|A||B|)_ij; 0 => 48              */
+  int32_t tau_bits;   /* split forms, per-panel slice choice: the smallest s    */
+                      /* whose modelled max error relative to (|A||B|)_ij is    */
+                      /* <= 2^-tau_bits (model: bits(s) against the panel's     */
+                      /* value spread and k); 0 => 48                           */
   int32_t staged;     /* FP64 path: 1 = always the register-staged kernel,      */
                       /* 0 = direct-to-LDS loads where alignment allows         */
   int32_t reserved[4];

@@ -319,6 +319,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   la.Wp = sa.Wp; la.nchunks = sa.Wp / hs::kSplitChunk;
   la.fixed_s = p->opts.slices; la.smin = p->opts.min_slices; la.smax = p->opts.max_slices;
   la.tau_bits = p->opts.tau_bits;
+  la.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
   la.zero_init = zero_init; la.persistent = p->opts.persistent;
   e = hs::launch_slices(p->fmt, la, grid, stream);
   if (e != hipSuccess) {

@@ -243,6 +243,20 @@ __global__ void zero_u32_kernel(uint32_t* p, int n) {
 }
 
 // ---- slice products + recombination -----------------------------------------
+// Slice count of a panel from its statistics.  ka, kb: log2 of the largest
+// kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
+// the max scaled error of the truncated s-slice product, fitted to the CPU
+// oracle at n = 16384 on uniform and exponent-spread (sigma = 2) entries:
+// log2 err ~ -bits(s) + 0.75 (ka + kb) + 1 - log2(k) / 2 (truncation errors
+// add with random signs over k, (|A||B|)_ij grows like k); bits(s) =
+// H + T (s - 1).  The smallest s whose estimate is within 2^-tau is taken.
+__device__ __forceinline__ int slice_policy(const SliceArgs& p, int H, int T) {
+  const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
+  const float need = (float)p.tau_bits + 0.75f * (ka + kb) + 1.0f - 0.5f * p.log2k;
+  const int s = (int)ceilf((need - (float)H) / (float)T) + 1;
+  return max(p.smin, min(p.smax, s));
+}
+
 template <int FMT, int SMAX, int WM, int WN>
 struct SliceTile {
   static constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
@@ -275,10 +289,7 @@ void slice_update_kernel(SliceArgs p) {
   // slice count of this panel: fixed, or from the split's exponent statistics
   int s = p.fixed_s;
   if (s <= 0) {
-    const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
-    const float need = (float)p.tau_bits - (float)H + log2f(exp2f(ka) + exp2f(kb));
-    s = (int)ceilf(need / (float)TB) + 1;
-    s = max(p.smin, min(p.smax, s));
+    s = slice_policy(p, H, TB);
   }
   s = max(1, min(SMAX, s));
   if (blockIdx.x == 0 && tid == 0 && p.slices_out) *p.slices_out = s;
@@ -522,6 +533,15 @@ constexpr int bf16_stages(int S) {
                                                           : 5;
 }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // Wait until at most k x PER of this wave's vector-memory instructions are
 // outstanding (k <= KMAX, known only at run time; the count is an immediate).
 template <int PER, int KMAX>
@@ -585,14 +605,8 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
     const int ub = wave * 64 + lane;
     const int colb = ub >> 1, halfb = (ub & 1) ^ ((colb >> 3) & 1);
     const uint32_t voffB = (uint32_t)(it.c0 + min(colb, it.w - 1)) * 32u + halfb * 16u;
-    // row of this lane's D item v in the item; exponents of the lane's 16
-    // rows and 2 columns (clamped into the item), fetched before the k loop
+    // row of this lane's D item v in the item
     auto erow = [&](int v) { return wm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3); };
-    int ea[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) ea[v] = p.eA[it.r0 + min(erow(v), it.h - 1)];
-    const int fb0c = p.fB[it.c0 + min(wn * 64 + l32, it.w - 1)];
-    const int fb1c = p.fB[it.c0 + min(wn * 64 + 32 + l32, it.w - 1)];
     auto dmaA = [&](int plane, int kb, uint8_t* dst) {
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           rsrcA, (__attribute__((address_space(3))) void*)dst, 16, voffA,
@@ -648,34 +662,42 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
     // zero: its first pair (row S-1-a, or row 0 for the shared deep one, with
     // l2 = 0) takes a zero C operand.
     const f16v zero = {};
-    auto row = [&](int set, int r, bool first) {
+    auto row = [&](int set, int r, int restart) {
       const int l1 = S - 1 - r;
 #pragma unroll
       for (int l2 = 0; l2 <= r; ++l2) {
         const int a = (l1 + l2) < NACC - 1 ? (l1 + l2) : NACC - 1;
-        const bool z = first && l2 == 0 && r == (a == NACC - 1 ? 0 : S - 1 - a);
+        const bool z = ((restart >> a) & 1) && l2 == 0 && r == (a == NACC - 1 ? 0 : S - 1 - a);
         acc0[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[set][l1], fb0[set][l2], z ? zero : acc0[a],
                                                           0, 0, 0);
         acc1[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[set][l1], fb1[set][l2], z ? zero : acc1[a],
                                                           0, 0, 0);
       }
     };
-    // every accumulator is added into the FP64 panel sum after each group of
-    // four steps (64 k), within the exactness bound of every level
-    auto flush = [&]() {
+    // Accumulator a is added into the FP64 panel sum every per(a) steps and
+    // then restarts from a zero C operand: every 8 steps (128 k) for levels
+    // 0 and 1 and the shared deep one, every 4 for levels 2 and 3, each
+    // within its exactness bound (level a may run 256/(a+1) k).  A flush adds
+    // the levels in the order of decreasing weight.  Runs of 8 steps are
+    // unrolled so that every flush and restart is static (longer runs raise
+    // the register pressure past the file); a remaining 4 steps flush every
+    // level.
+    auto flush = [&](int mask) {
 #pragma unroll
       for (int a = 0; a < NACC; ++a)
+        if ((mask >> a) & 1) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          cp0[v] += (double)acc0[a][v];
-          cp1[v] += (double)acc1[a][v];
+          for (int v = 0; v < 16; ++v) {
+            cp0[v] += (double)acc0[a][v];
+            cp1[v] += (double)acc1[a][v];
+          }
         }
     };
     // one 16-k step: fragments of step ci are in set `cur`.  The barrier sits
     // before row S-LAG: by then every fragment of step ci has been read
     // (ring_barrier retires the reads), so stage ci is free for the DMA of
     // step ci+NS, and stage ci+1 is complete for every wave.
-    auto step = [&](int ci, int cur, bool first) {
+    auto step = [&](int ci, int cur, int restart) {
       const int nxt = cur ^ 1;
       const bool more = ci + 1 < nsteps;
 #pragma unroll
@@ -687,9 +709,22 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
         }
         if (r + LAG < S) read_row(cur, ci % NS, r + LAG);
         else if (more) read_row(nxt, (ci + 1) % NS, r + LAG - S);
-        row(cur, r, first);
+        row(cur, r, restart);
         __builtin_amdgcn_sched_barrier(0);
       }
+    };
+    constexpr int ALL = (1 << NACC) - 1;
+    // levels whose run starts (ends) at step j of an 8-step run
+    auto per = [](int a) { return a <= 1 || a >= 4 ? 8 : 4; };
+    auto starts = [&](int j) {
+      int m = 0;
+      for (int a = 0; a < NACC; ++a) m |= (j % per(a) == 0) << a;
+      return m;
+    };
+    auto ends = [&](int j) {
+      int m = 0;
+      for (int a = 0; a < NACC; ++a) m |= ((j + 1) % per(a) == 0) << a;
+      return m;
     };
 
     // prologue: NS steps in flight, then the first LAG rows of step 0
@@ -701,36 +736,49 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
 #pragma unroll
     for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
 
-    for (int ci = 0; ci < nsteps; ci += 4) {
-      step(ci, 0, true);
-      step(ci + 1, 1, false);
-      step(ci + 2, 0, false);
-      step(ci + 3, 1, false);
-      flush();
+    int ci = 0;
+    for (; ci + 8 <= nsteps; ci += 8) {
+      static_for<0, 8>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        step(ci + j, j & 1, starts(j));
+        flush(ends(j));
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    }
+    for (; ci < nsteps; ci += 4) {
+      step(ci, 0, ALL);
+      step(ci + 1, 1, 0);
+      step(ci + 2, 0, 0);
+      step(ci + 3, 1, 0);
+      flush(ALL);
     }
     __syncthreads();  // the ring is reused by the next item
 
     // C += 2^(e_i + f_j - 16) x panel sum.  Addresses are clamped into the
     // item so that every load is unconditional (all in flight at once); only
     // the stores are predicated.
-    double cold0[16], cold1[16];
-    if (!p.zero_init) {
+    // exponents of the lane's 16 rows (clamped into the item)
+    int ea[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) ea[v] = p.eA[it.r0 + min(erow(v), it.h - 1)];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {         // one 32-column block at a time
+      const int col = wn * 64 + q * 32 + l32;
+      const int fq = p.fB[it.c0 + min(col, it.w - 1)];
+      double cold[16];
+      if (!p.zero_init) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          cold[v] = p.C[(int64_t)(it.r0 + min(erow(v), it.h - 1)) * p.ldc + it.c0 +
+                        min(col, it.w - 1)];
+      }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const double* crow = p.C + (int64_t)(it.r0 + min(erow(v), it.h - 1)) * p.ldc + it.c0;
-        cold0[v] = crow[min(wn * 64 + l32, it.w - 1)];
-        cold1[v] = crow[min(wn * 64 + 32 + l32, it.w - 1)];
+        const int row = erow(v);
+        const double add = ldexp(q ? cp1[v] : cp0[v], ea[v] + fq - 16);
+        if (row < it.h && col < it.w)
+          p.C[(int64_t)(it.r0 + row) * p.ldc + it.c0 + col] = p.zero_init ? add : cold[v] + add;
       }
-    }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = erow(v);
-      double* crow = p.C + (int64_t)(it.r0 + row) * p.ldc + it.c0;
-      const int col0 = wn * 64 + l32, col1 = col0 + 32;
-      const double add0 = ldexp(cp0[v], ea[v] + fb0c - 16);
-      const double add1 = ldexp(cp1[v], ea[v] + fb1c - 16);
-      if (row < it.h && col0 < it.w) crow[col0] = p.zero_init ? add0 : cold0[v] + add0;
-      if (row < it.h && col1 < it.w) crow[col1] = p.zero_init ? add1 : cold1[v] + add1;
     }
   }
 }
@@ -739,10 +787,7 @@ __global__ __launch_bounds__(256, 1) void slice_bf16_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
   int s = p.fixed_s;
   if (s <= 0) {
-    const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
-    const float need = (float)p.tau_bits - 8.0f + log2f(exp2f(ka) + exp2f(kb));
-    s = (int)ceilf(need / 9.0f) + 1;
-    s = max(p.smin, min(p.smax, s));
+    s = slice_policy(p, 8, 9);
   }
   s = max(1, min(kSplitMaxSlices, s));
   if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;

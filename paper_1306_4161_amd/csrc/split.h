@@ -30,6 +30,7 @@ struct SliceArgs {
   const WorkItem* items; int32_t nitems; int32_t per_xcd;
   int32_t Wp, nchunks;
   int32_t fixed_s, smin, smax, tau_bits;
+  float log2k;                       // log2 of the product's inner dimension k
   int32_t zero_init, persistent;
 };
 
