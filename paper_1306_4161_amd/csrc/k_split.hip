@@ -58,188 +58,86 @@ __device__ inline uint8_t e4m3_of_int(int d) {
 // plane * plane_stride + (kk / 16) * rows * 16 + row * 16 + kk % 16, so that
 // the 16 k of one row of one block are contiguous and one block of a plane
 // (all rows) is one contiguous run, the unit the product kernel streams.
-template <int FMT>
-__device__ inline void split_value(double a, int e, int smax, uint16_t* out16, uint8_t* out8,
-                                   int64_t plane_stride, int64_t pos) {
-  constexpr int H = FMT == 0 ? 8 : 4;
-  constexpr int T = FMT == 0 ? 9 : 5;
-  double r = ldexp(a, -e);
-  int shift = H;
-  for (int l = 0; l < smax; ++l) {
-    const double y = ldexp(r, shift);
-    const double d = rint(y);
-    r = y - d;
-    shift = T;
-    if (FMT == 0) {
-      const float f = (float)ldexp(d, -T * l);  // d 2^(-T l): <= 9 significant bits
-      out16[l * plane_stride + pos] = (uint16_t)(__float_as_uint(f) >> 16);
-    } else {
-      out8[l * plane_stride + pos] = e4m3_of_int((int)d);
-    }
-  }
-}
 
-// ---- A rows: one half-wave per row ----------------------------------------------
-// Each lane owns 8 consecutive k of every 256-k piece of the row and writes
-// its digits of one plane as one 16-byte (BF16) or 8-byte (FP8) group.
-template <int FMT>
-__global__ __launch_bounds__(256) void split_rows_kernel(SplitArgs p) {
+// ---- split, one kernel per operand: 64 lines (A rows or B columns) per block --
+// Unit of work: one line and one 16-k block.  Lane = line, wave = k16 block of
+// a 64-k chunk.  The digits of a unit are 16 consecutive elements of one
+// plane (32 bytes in BF16), and consecutive lines are consecutive units of
+// the k16-block-major layout, so each wave stores 64 x 32 contiguous bytes
+// per plane.  A rows are read 16 contiguous doubles per lane; B columns one
+// 512-byte row segment per wave-load.  Two passes over the panel: the
+// line's max and sum (exponent, kappa), then the digits.
+template <int FMT, bool COLS>
+__global__ __launch_bounds__(256) void split_lines_kernel(SplitArgs p) {
   constexpr int H = FMT == 0 ? 8 : 4;
   constexpr int T = FMT == 0 ? 9 : 5;
-  const int hw = threadIdx.x >> 5, hl = threadIdx.x & 31;
-  const int i = blockIdx.x * 8 + hw;
-  if (i >= p.m) return;  // the half-wave leaves; shuffles below stay inside a half-wave
-  const double* row = p.A + (int64_t)i * p.lda + p.k0;
+  __shared__ double red_mx[4][64], red_sm[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nl = COLS ? p.n : p.m;
+  const int line = blockIdx.x * 64 + lane;
+  const bool valid = line < nl;
+  const int ln = valid ? line : nl - 1;      // clamped (loads only)
+  // element (line, kk) of the panel
+  auto at = [&](int kk) -> double {
+    return COLS ? p.B[(int64_t)(p.k0 + kk) * p.ldb + ln] : p.A[(int64_t)ln * p.lda + p.k0 + kk];
+  };
   double mx = 0.0, sm = 0.0;
-  for (int kk = hl * 8; kk < p.w; kk += 256) {
+  for (int k0 = wave * 16; k0 < p.w; k0 += 64) {
+    double x[16];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (kk + e < p.w) {
-        const double a = fabs(row[kk + e]);
-        mx = fmax(mx, a);
-        sm += a;
-      }
+    for (int q = 0; q < 16; ++q) x[q] = k0 + q < p.w ? fabs(at(k0 + q)) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      mx = fmax(mx, x[q]);
+      sm += x[q];
     }
   }
-  for (int o = 16; o > 0; o >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, o, 32));
-    sm += __shfl_xor(sm, o, 32);
-  }
+  red_mx[wave][lane] = mx;
+  red_sm[wave][lane] = sm;
+  __syncthreads();
+  mx = fmax(fmax(red_mx[0][lane], red_mx[1][lane]), fmax(red_mx[2][lane], red_mx[3][lane]));
+  sm = (red_sm[0][lane] + red_sm[1][lane]) + (red_sm[2][lane] + red_sm[3][lane]);
   const int e = exponent_bound(mx);
-  if (hl == 0) {
-    p.eA[i] = e;
+  if (wave == 0 && valid) {
+    (COLS ? p.fB : p.eA)[line] = e;
     if (sm > 0.0) {
       const float kap = (float)log2(mx * (double)p.w / sm);
-      atomicMax(&p.stats[0], __float_as_uint(fmaxf(kap, 0.0f)));
+      atomicMax(&p.stats[COLS ? 1 : 0], __float_as_uint(fmaxf(kap, 0.0f)));
     }
   }
-  const int64_t blk = (int64_t)p.m * 16;     // elements per k16 block of a plane
-  for (int kk = hl * 8; kk < p.Wp; kk += 256) {
-    double r[8];
+  uint8_t* dig = (uint8_t*)(COLS ? p.digB : p.digA);
+  const int64_t plane = COLS ? p.planeB : p.planeA;   // elements per plane
+  const int64_t blk = (int64_t)nl * 16;                // elements per k16 block
+  constexpr int ESZ = FMT == 0 ? 2 : 1;
+  for (int k0 = wave * 16; k0 < p.Wp; k0 += 64) {
+    double r[16];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] = ldexp(kk + q < p.w ? row[kk + q] : 0.0, -e);
-    const int64_t pos = (int64_t)(kk >> 4) * blk + (int64_t)i * 16 + (kk & 15);
+    for (int q = 0; q < 16; ++q) r[q] = ldexp(k0 + q < p.w ? at(k0 + q) : 0.0, -e);
+    if (!valid) continue;
+    const int64_t pos = (int64_t)(k0 >> 4) * blk + (int64_t)line * 16;
     int shift = H;
     for (int l = 0; l < p.smax; ++l) {
-      uint32_t w32[4] = {0u, 0u, 0u, 0u};
+      uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 16; ++q) {
         const double y = ldexp(r[q], shift);
         const double d = rint(y);
         r[q] = y - d;
-        uint32_t bits;
         if (FMT == 0)
-          bits = __float_as_uint((float)ldexp(d, -T * l)) >> 16;  // d 2^(-T l), exact
+          w32[q >> 1] |= (__float_as_uint((float)ldexp(d, -T * l)) >> 16) << (16 * (q & 1));
         else
-          bits = e4m3_of_int((int)d);
-        if (FMT == 0)
-          w32[q >> 1] |= bits << (16 * (q & 1));
-        else
-          w32[q >> 2] |= bits << (8 * (q & 3));
+          w32[q >> 2] |= (uint32_t)e4m3_of_int((int)d) << (8 * (q & 3));
       }
       shift = T;
-      if (FMT == 0)
-        *(uint4*)((uint16_t*)p.digA + l * p.planeA + pos) = make_uint4(w32[0], w32[1], w32[2], w32[3]);
-      else
-        *(uint2*)((uint8_t*)p.digA + l * p.planeA + pos) = make_uint2(w32[0], w32[1]);
-    }
-  }
-}
-
-// ---- B columns: 64 columns per workgroup, digits written transposed ----------
-template <int FMT>
-__global__ __launch_bounds__(256) void split_cols_kernel(SplitArgs p) {
-  constexpr int PADE = 8;                    // row padding (elements)
-  constexpr int RS = 64 + PADE;              // LDS row stride (elements)
-  __shared__ double red_mx[4][64], red_sm[4][64];
-  __shared__ int sexp[64];
-  __shared__ uint16_t tile[kSplitMaxSlices * 64 * RS];
-
-  const int tid = threadIdx.x;
-  const int c = tid & 63, part = tid >> 6;
-  const int j0 = blockIdx.x * 64;
-  const int j = j0 + c;
-  const bool valid = j < p.n;
-  const double* col = p.B + (int64_t)p.k0 * p.ldb + j;
-
-  double mx = 0.0, sm = 0.0;
-  if (valid)
-    for (int r = part; r < p.w; r += 4) {
-      const double v = fabs(col[(int64_t)r * p.ldb]);
-      mx = fmax(mx, v);
-      sm += v;
-    }
-  red_mx[part][c] = mx;
-  red_sm[part][c] = sm;
-  __syncthreads();
-  if (part == 0) {
-    for (int q = 1; q < 4; ++q) {
-      mx = fmax(mx, red_mx[q][c]);
-      sm += red_sm[q][c];
-    }
-    const int f = exponent_bound(mx);
-    sexp[c] = f;
-    float kap = 0.0f;
-    if (valid) {
-      p.fB[j] = f;
-      if (sm > 0.0) kap = fmaxf((float)log2(mx * (double)p.w / sm), 0.0f);
-    }
-    for (int o = 32; o > 0; o >>= 1) kap = fmaxf(kap, __shfl_xor(kap, o));
-    if (c == 0) atomicMax(&p.stats[1], __float_as_uint(kap));
-  }
-  __syncthreads();
-  const int f = sexp[c];
-
-  for (int rb = 0; rb < p.Wp; rb += 64) {
-    for (int u = 0; u < 16; ++u) {
-      const int kl = part * 16 + u;
-      const int kk = rb + kl;
-      const double v = (valid && kk < p.w) ? col[(int64_t)kk * p.ldb] : 0.0;
-      constexpr int H = FMT == 0 ? 8 : 4;
-      constexpr int T = FMT == 0 ? 9 : 5;
-      double r = ldexp(v, -f);
-      int shift = H;
-      for (int l = 0; l < p.smax; ++l) {
-        const double y = ldexp(r, shift);
-        const double d = rint(y);
-        r = y - d;
-        shift = T;
-        uint16_t bits;
-        if (FMT == 0)
-          bits = (uint16_t)(__float_as_uint((float)ldexp(d, -T * l)) >> 16);
-        else
-          bits = e4m3_of_int((int)d);
-        tile[(l * 64 + c) * RS + kl] = bits;
+      uint8_t* dst = dig + (l * plane + pos) * ESZ;
+      if (FMT == 0) {
+        ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
+        ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
+      } else {
+        ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
       }
     }
-    __syncthreads();
-    // write out: 64 columns x 64 k per plane, 16 elements per thread
-    const int cc = tid >> 2, seg = tid & 3;
-    if (j0 + cc < p.n) {
-      for (int l = 0; l < p.smax; ++l) {
-        const uint16_t* src = tile + (l * 64 + cc) * RS + seg * 16;
-        const int64_t pos = (int64_t)((rb >> 4) + seg) * p.n * 16 + (int64_t)(j0 + cc) * 16;
-        if (FMT == 0) {
-          uint4* dst = (uint4*)((uint16_t*)p.digB + l * p.planeB + pos);
-          const uint4* s4 = (const uint4*)src;
-          dst[0] = s4[0];
-          dst[1] = s4[1];
-        } else {
-          uint32_t w[4];
-          for (int q = 0; q < 4; ++q)
-            w[q] = (uint32_t)src[4 * q] | ((uint32_t)src[4 * q + 1] << 8) |
-                   ((uint32_t)src[4 * q + 2] << 16) | ((uint32_t)src[4 * q + 3] << 24);
-          *(uint4*)((uint8_t*)p.digB + l * p.planeB + pos) = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-      }
-    }
-    __syncthreads();
   }
-}
-
-__global__ void zero_u32_kernel(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
 }
 
 // ---- slice products + recombination -----------------------------------------
@@ -848,13 +746,13 @@ hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float
 
 // ---- launchers ----------------------------------------------------------------
 hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
-  const int gr = (a.m + 7) / 8, gc = (a.n + 63) / 64;
+  const int gr = (a.m + 63) / 64, gc = (a.n + 63) / 64;
   if (a.fmt == 0) {
-    hipLaunchKernelGGL(split_rows_kernel<0>, dim3(gr), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(split_cols_kernel<0>, dim3(gc), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((split_lines_kernel<0, false>), dim3(gr), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((split_lines_kernel<0, true>), dim3(gc), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL(split_rows_kernel<1>, dim3(gr), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(split_cols_kernel<1>, dim3(gc), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((split_lines_kernel<1, false>), dim3(gr), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((split_lines_kernel<1, true>), dim3(gc), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
