@@ -140,6 +140,12 @@ __global__ __launch_bounds__(256) void split_lines_kernel(SplitArgs p) {
   }
 }
 
+// clears the per-panel statistics before the split of a panel
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // ---- slice products + recombination -----------------------------------------
 // Slice count of a panel from its statistics.  ka, kb: log2 of the largest
 // kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
