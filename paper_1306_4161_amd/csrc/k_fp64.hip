@@ -421,6 +421,7 @@ const std::vector<Fp64Entry>& table() {
       HS_FP64(128, 128, 16, 2, 2, 2),
       HS_FP64(128, 128, 8, 2, 2, 2),
       HS_FP64(256, 128, 8, 4, 2, 1),
+      HS_FP64(256, 128, 16, 4, 2, 1),
       HS_FP64(128, 64, 8, 2, 2, 2),
       HS_FP64(128, 128, 32, 2, 2, 1),
       HS_FP64(128, 64, 16, 2, 2, 2),
@@ -435,17 +436,19 @@ const std::vector<Fp64Entry>& table() {
 struct DmaEntry {
   TileCfg cfg;
   void (*kern)(UpdateArgs);
+  int threads;
   int occupancy;
 };
-#define HS_DMA(TM, TN, NS, OCC) \
-  DmaEntry{TileCfg{TM, TN, 16}, fp64_dma_kernel<TM, TN, NS, 2, 2, OCC>, OCC}
+#define HS_DMA(TM, TN, NS, WM, WN, OCC) \
+  DmaEntry{TileCfg{TM, TN, 16}, fp64_dma_kernel<TM, TN, NS, WM, WN, OCC>, WM * WN * 64, OCC}
 // direct-to-LDS kernels, keyed by the staged kernel configuration they replace
 const std::vector<DmaEntry>& dma_table() {
   static const std::vector<DmaEntry> t = {
-      HS_DMA(128, 128, 2, 2),
-      HS_DMA(64, 64, 4, 2),
-      HS_DMA(128, 64, 3, 2),
-      HS_DMA(64, 128, 3, 2),
+      HS_DMA(128, 128, 2, 2, 2, 2),
+      HS_DMA(256, 128, 3, 4, 2, 1),
+      HS_DMA(64, 64, 4, 2, 2, 2),
+      HS_DMA(128, 64, 3, 2, 2, 2),
+      HS_DMA(64, 128, 3, 2, 2, 2),
   };
   return t;
 }
@@ -477,7 +480,7 @@ hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStr
   if (dma) {
     for (auto& e : dma_table()) {
       if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) {
-        hipLaunchKernelGGL(e.kern, dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(e.kern, dim3(grid), dim3(e.threads), 0, s, a);
         return hipGetLastError();
       }
     }

@@ -31,6 +31,7 @@ CANDIDATES = [
     ("fp64_128x128x8", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=8)),
     ("fp64_128x128x32", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=32)),
     ("fp64_256x128x8", dict(prec=hs.FP64, tile_m=256, tile_n=128, kc=8)),
+    ("fp64_256x128x16", dict(prec=hs.FP64, tile_m=256, tile_n=128, kc=16)),
     ("fp64_128x64x16", dict(prec=hs.FP64, tile_m=128, tile_n=64, kc=16)),
     ("fp64_64x128x16", dict(prec=hs.FP64, tile_m=64, tile_n=128, kc=16)),
     ("fp64_64x64x16", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=16)),

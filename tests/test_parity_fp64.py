@@ -121,9 +121,12 @@ def test_schedule_invariance_bitwise():
         p = hs.Plan(n, c["P"], c["Q"], c["G"], 32, c["M"])
         assert np.array_equal(_run(p, A, B), ref), c
     for tm, tn, kc in [(128, 128, 16), (128, 128, 32), (64, 64, 32), (128, 64, 16),
-                       (64, 128, 16), (32, 32, 16)]:
+                       (64, 128, 16), (32, 32, 16), (256, 128, 16), (256, 128, 8)]:
         p = hs.Plan(n, 4, 4, 4, 32, 64, tile_m=tm, tile_n=tn, kc=kc)
         assert np.array_equal(_run(p, A, B), ref), (tm, tn, kc)
+        # 1 x 2 grid: 512 x 256 tiles, so every macro-tile is full
+        p = hs.Plan(n, 1, 2, 1, 32, 64, tile_m=tm, tile_n=tn, kc=kc)
+        assert np.array_equal(_run(p, A, B), ref), ("full", tm, tn, kc)
     p = hs.Plan(n, 4, 4, 4, 32, 64, persistent=1)
     assert np.array_equal(_run(p, A, B), ref)
     p = hs.Plan(n, 4, 4, 4, 32, 64, dist=hs.DIST_BLOCK_CYCLIC, nb=64)
