@@ -174,8 +174,10 @@ int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, voi
  * FP8-e4m3 digit, stored k16-block-major: digit (plane, row, k) at
  * plane*m*Wp + (k/16)*m*16 + row*16 + k%16), the B digit planes (the same
  * with n columns: B transposed), the int32 row exponents of A and column
- * exponents of B.  They hold the most recently split panel.  Lets a
- * caller inspect the split; HSUMMA_ERR_UNSUPPORTED for the FP64 path.
+ * exponents of B.  They hold the most recently split panel; of its planes
+ * only the first s (its slice count, see hsumma_panel_slices) are written.
+ * Lets a caller inspect the split; HSUMMA_ERR_UNSUPPORTED for the FP64
+ * path.
  */
 int hsumma_split_layout(hsumma_plan_t plan, size_t* off_digA, size_t* off_digB,
                         size_t* off_eA, size_t* off_fB, int32_t* Wp, int32_t* planes);

@@ -182,7 +182,7 @@ void build_items(hsumma_plan_s& p) {
   p.items_even = true;
   for (auto& it : p.items)
     if ((it.c0 | it.w) & 1) p.items_even = false;
-  if (p.opts.persistent) {
+  if (p.opts.persistent || p.fmt == 0) {
     // Longest-processing-time order inside each XCD's list, so that the
     // static round-robin of the persistent workgroups stays balanced when
     // tiles are uneven (ragged block-cyclic edges).
@@ -244,7 +244,10 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   if (rc) return rc;
   if (p->items.empty()) return HSUMMA_OK;
   int grid = 8 * p->per_xcd;
-  if (p->opts.persistent) {
+  // the BF16 slice kernel always runs persistent (one workgroup per CU over
+  // its XCD's longest-first item list; measured as fast or faster)
+  const bool persistent = p->opts.persistent || p->fmt == 0;
+  if (persistent) {
     int dev = 0, cus = 0;
     HS_CHECK_HIP(hipGetDevice(&dev));
     HS_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -293,6 +296,8 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   sa.Wp = (int32_t)(((k1 - k0) + pad - 1) / pad * pad);
   sa.fmt = p->fmt;
   sa.smax = p->opts.max_slices;
+  sa.fixed_s = p->opts.slices; sa.smin = p->opts.min_slices; sa.tau_bits = p->opts.tau_bits;
+  sa.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
   sa.digA = w8 + p->off_digA; sa.planeA = (int64_t)p->m * sa.Wp;
   sa.digB = w8 + p->off_digB; sa.planeB = (int64_t)p->n * sa.Wp;
   sa.eA = (int32_t*)(w8 + p->off_eA); sa.fB = (int32_t*)(w8 + p->off_fB);
@@ -320,7 +325,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   la.fixed_s = p->opts.slices; la.smin = p->opts.min_slices; la.smax = p->opts.max_slices;
   la.tau_bits = p->opts.tau_bits;
   la.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
-  la.zero_init = zero_init; la.persistent = p->opts.persistent;
+  la.zero_init = zero_init; la.persistent = persistent ? 1 : 0;
   e = hs::launch_slices(p->fmt, la, grid, stream);
   if (e != hipSuccess) {
     set_error(std::string("slice products launch: ") + hipGetErrorString(e));

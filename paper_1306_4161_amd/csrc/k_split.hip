@@ -59,33 +59,58 @@ __device__ inline uint8_t e4m3_of_int(int d) {
 // the 16 k of one row of one block are contiguous and one block of a plane
 // (all rows) is one contiguous run, the unit the product kernel streams.
 
-// ---- split, one kernel per operand: 64 lines (A rows or B columns) per block --
-// Unit of work: one line and one 16-k block.  Lane = line, wave = k16 block of
-// a 64-k chunk.  The digits of a unit are 16 consecutive elements of one
-// plane (32 bytes in BF16), and consecutive lines are consecutive units of
-// the k16-block-major layout, so each wave stores 64 x 32 contiguous bytes
-// per plane.  A rows are read 16 contiguous doubles per lane; B columns one
-// 512-byte row segment per wave-load.  Two passes over the panel: the
-// line's max and sum (exponent, kappa), then the digits.
-template <int FMT, bool COLS>
-__global__ __launch_bounds__(256) void split_lines_kernel(SplitArgs p) {
-  constexpr int H = FMT == 0 ? 8 : 4;
-  constexpr int T = FMT == 0 ? 9 : 5;
-  __shared__ double red_mx[4][64], red_sm[4][64];
+// Slice count of a panel from its statistics.  ka, kb: log2 of the largest
+// kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
+// the max scaled error of the truncated s-slice product, fitted to the CPU
+// oracle at n = 16384 on uniform and exponent-spread (sigma = 2) entries:
+// log2 err ~ -bits(s) + 0.75 (ka + kb) + 1 - log2(k) / 2 (truncation errors
+// add with random signs over k, (|A||B|)_ij grows like k); bits(s) =
+// H + T (s - 1).  The smallest s whose estimate is within 2^-tau is taken
+// (or the fixed count), clamped to [smin, smax] and to the planes stored.
+// The split's digit pass and the product kernels evaluate it identically.
+__device__ __forceinline__ int panel_slices(const uint32_t* stats, int fixed_s, int smin, int smax,
+                                            int tau_bits, float log2k, int H, int T) {
+  int s = fixed_s;
+  if (s <= 0) {
+    const float ka = __uint_as_float(stats[0]), kb = __uint_as_float(stats[1]);
+    const float need = (float)tau_bits + 0.75f * (ka + kb) + 1.0f - 0.5f * log2k;
+    s = (int)ceilf((need - (float)H) / (float)T) + 1;
+    s = max(smin, min(smax, s));
+  }
+  return max(1, min(kSplitMaxSlices, s));
+}
+
+// ---- split: statistics pass, then digit pass; 64 lines per block ------------
+// A line is a row of A or a column of B.  Lane = line, wave w = the 16-k
+// blocks w, w + 8, w + 16, ...  The digits of a (line, k16 block) unit are 16
+// consecutive elements of one plane (32 bytes in BF16), and consecutive
+// lines are consecutive units of the k16-block-major layout, so each wave
+// stores 64 x 32 contiguous bytes per plane.  A rows are read 16 contiguous
+// doubles per lane; B columns one 512-byte row segment per wave-load.  The
+// statistics pass writes each line's exponent and the panel's kappa; the
+// digit pass then knows the panel's slice count and writes only those
+// planes.  Both passes run over A's and B's blocks in one launch each.
+template <bool COLS>
+__device__ __forceinline__ double panel_at(const SplitArgs& p, int ln, int kk) {
+  return COLS ? p.B[(int64_t)(p.k0 + kk) * p.ldb + ln] : p.A[(int64_t)ln * p.lda + p.k0 + kk];
+}
+
+constexpr int kSplitWaves = 8;                // waves per block of 64 lines
+
+template <bool COLS>
+__device__ void split_stats_lines(const SplitArgs& p, int blk) {
+  constexpr int NW = kSplitWaves;
+  __shared__ double red_mx[NW][64], red_sm[NW][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nl = COLS ? p.n : p.m;
-  const int line = blockIdx.x * 64 + lane;
+  const int line = blk * 64 + lane;
   const bool valid = line < nl;
   const int ln = valid ? line : nl - 1;      // clamped (loads only)
-  // element (line, kk) of the panel
-  auto at = [&](int kk) -> double {
-    return COLS ? p.B[(int64_t)(p.k0 + kk) * p.ldb + ln] : p.A[(int64_t)ln * p.lda + p.k0 + kk];
-  };
   double mx = 0.0, sm = 0.0;
-  for (int k0 = wave * 16; k0 < p.w; k0 += 64) {
+  for (int k0 = wave * 16; k0 < p.w; k0 += 16 * NW) {
     double x[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = k0 + q < p.w ? fabs(at(k0 + q)) : 0.0;
+    for (int q = 0; q < 16; ++q) x[q] = k0 + q < p.w ? fabs(panel_at<COLS>(p, ln, k0 + q)) : 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       mx = fmax(mx, x[q]);
@@ -95,28 +120,46 @@ __global__ __launch_bounds__(256) void split_lines_kernel(SplitArgs p) {
   red_mx[wave][lane] = mx;
   red_sm[wave][lane] = sm;
   __syncthreads();
-  mx = fmax(fmax(red_mx[0][lane], red_mx[1][lane]), fmax(red_mx[2][lane], red_mx[3][lane]));
-  sm = (red_sm[0][lane] + red_sm[1][lane]) + (red_sm[2][lane] + red_sm[3][lane]);
-  const int e = exponent_bound(mx);
-  if (wave == 0 && valid) {
-    (COLS ? p.fB : p.eA)[line] = e;
-    if (sm > 0.0) {
-      const float kap = (float)log2(mx * (double)p.w / sm);
-      atomicMax(&p.stats[COLS ? 1 : 0], __float_as_uint(fmaxf(kap, 0.0f)));
-    }
+  if (wave != 0 || !valid) return;
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    mx = fmax(mx, red_mx[w][lane]);
+    sm += red_sm[w][lane];
   }
+  (COLS ? p.fB : p.eA)[line] = exponent_bound(mx);
+  if (sm > 0.0) {
+    const float kap = (float)log2(mx * (double)p.w / sm);
+    atomicMax(&p.stats[COLS ? 1 : 0], __float_as_uint(fmaxf(kap, 0.0f)));
+  }
+}
+
+__global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs p) {
+  const int ga = (p.m + 63) / 64;
+  if ((int)blockIdx.x < ga) split_stats_lines<false>(p, blockIdx.x);
+  else split_stats_lines<true>(p, blockIdx.x - ga);
+}
+
+template <int FMT, bool COLS>
+__device__ void split_digit_lines(const SplitArgs& p, int blk, int s) {
+  constexpr int H = FMT == 0 ? 8 : 4;
+  constexpr int T = FMT == 0 ? 9 : 5;
+  constexpr int ESZ = FMT == 0 ? 2 : 1;
+  constexpr int NW = kSplitWaves;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nl = COLS ? p.n : p.m;
+  const int line = blk * 64 + lane;
+  if (line >= nl) return;                    // no barrier follows
+  const int e = (COLS ? p.fB : p.eA)[line];
   uint8_t* dig = (uint8_t*)(COLS ? p.digB : p.digA);
   const int64_t plane = COLS ? p.planeB : p.planeA;   // elements per plane
-  const int64_t blk = (int64_t)nl * 16;                // elements per k16 block
-  constexpr int ESZ = FMT == 0 ? 2 : 1;
-  for (int k0 = wave * 16; k0 < p.Wp; k0 += 64) {
+  const int64_t blkel = (int64_t)nl * 16;              // elements per k16 block
+  for (int k0 = wave * 16; k0 < p.Wp; k0 += 16 * NW) {
     double r[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) r[q] = ldexp(k0 + q < p.w ? at(k0 + q) : 0.0, -e);
-    if (!valid) continue;
-    const int64_t pos = (int64_t)(k0 >> 4) * blk + (int64_t)line * 16;
+    for (int q = 0; q < 16; ++q) r[q] = ldexp(k0 + q < p.w ? panel_at<COLS>(p, line, k0 + q) : 0.0, -e);
+    const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
     int shift = H;
-    for (int l = 0; l < p.smax; ++l) {
+    for (int l = 0; l < s; ++l) {
       uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -130,14 +173,19 @@ __global__ __launch_bounds__(256) void split_lines_kernel(SplitArgs p) {
       }
       shift = T;
       uint8_t* dst = dig + (l * plane + pos) * ESZ;
-      if (FMT == 0) {
-        ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
-        ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
-      } else {
-        ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
-      }
+      ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
+      if (FMT == 0) ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
     }
   }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArgs p) {
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k,
+                             FMT == 0 ? 8 : 4, FMT == 0 ? 9 : 5);
+  const int ga = (p.m + 63) / 64;
+  if ((int)blockIdx.x < ga) split_digit_lines<FMT, false>(p, blockIdx.x, s);
+  else split_digit_lines<FMT, true>(p, blockIdx.x - ga, s);
 }
 
 // clears the per-panel statistics before the split of a panel
@@ -147,19 +195,6 @@ __global__ void zero_u32_kernel(uint32_t* p, int n) {
 }
 
 // ---- slice products + recombination -----------------------------------------
-// Slice count of a panel from its statistics.  ka, kb: log2 of the largest
-// kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
-// the max scaled error of the truncated s-slice product, fitted to the CPU
-// oracle at n = 16384 on uniform and exponent-spread (sigma = 2) entries:
-// log2 err ~ -bits(s) + 0.75 (ka + kb) + 1 - log2(k) / 2 (truncation errors
-// add with random signs over k, (|A||B|)_ij grows like k); bits(s) =
-// H + T (s - 1).  The smallest s whose estimate is within 2^-tau is taken.
-__device__ __forceinline__ int slice_policy(const SliceArgs& p, int H, int T) {
-  const float ka = __uint_as_float(p.stats[0]), kb = __uint_as_float(p.stats[1]);
-  const float need = (float)p.tau_bits + 0.75f * (ka + kb) + 1.0f - 0.5f * p.log2k;
-  const int s = (int)ceilf((need - (float)H) / (float)T) + 1;
-  return max(p.smin, min(p.smax, s));
-}
 
 template <int FMT, int SMAX, int WM, int WN>
 struct SliceTile {
@@ -191,11 +226,7 @@ void slice_update_kernel(SliceArgs p) {
   const int l16 = lane & 15, lq = lane >> 4;
 
   // slice count of this panel: fixed, or from the split's exponent statistics
-  int s = p.fixed_s;
-  if (s <= 0) {
-    s = slice_policy(p, H, TB);
-  }
-  s = max(1, min(SMAX, s));
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, H, TB);
   if (blockIdx.x == 0 && tid == 0 && p.slices_out) *p.slices_out = s;
 
   const int bid = blockIdx.x;
@@ -689,11 +720,7 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
 
 __global__ __launch_bounds__(256, 1) void slice_bf16_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
-  int s = p.fixed_s;
-  if (s <= 0) {
-    s = slice_policy(p, 8, 9);
-  }
-  s = max(1, min(kSplitMaxSlices, s));
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, 8, 9);
   if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
   switch (s) {
     case 1: slice_bf16_items<1>(p, smem); break;
@@ -752,14 +779,12 @@ hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float
 
 // ---- launchers ----------------------------------------------------------------
 hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
-  const int gr = (a.m + 63) / 64, gc = (a.n + 63) / 64;
-  if (a.fmt == 0) {
-    hipLaunchKernelGGL((split_lines_kernel<0, false>), dim3(gr), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((split_lines_kernel<0, true>), dim3(gc), dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((split_lines_kernel<1, false>), dim3(gr), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((split_lines_kernel<1, true>), dim3(gc), dim3(256), 0, s, a);
-  }
+  const int g = (a.m + 63) / 64 + (a.n + 63) / 64;
+  hipLaunchKernelGGL(split_stats_kernel, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+  if (a.fmt == 0)
+    hipLaunchKernelGGL(split_digits_kernel<0>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+  else
+    hipLaunchKernelGGL(split_digits_kernel<1>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ struct SplitArgs {
   void* digB; int64_t planeB;        // planes of n x Wp digits (B transposed)
   int32_t* eA; int32_t* fB;          // per-row / per-column exponents
   uint32_t* stats;                   // [0]: max log2 kappa over A rows, [1]: over B cols
+  int32_t fixed_s, smin, tau_bits;   // slice-count choice (as in SliceArgs)
+  float log2k;
 };
 
 struct SliceArgs {
@@ -34,6 +36,8 @@ struct SliceArgs {
   int32_t zero_init, persistent;
 };
 
+// Statistics pass (exponents, kappa) over both operands, then the digit
+// pass, which writes only the panel's chosen number of planes.
 hipError_t launch_split(const SplitArgs& a, hipStream_t s);
 hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);

@@ -90,6 +90,8 @@ def test_digit_planes_match_oracle_bitwise(prec, fmt):
     C, ws = _run(p, A, B)
     lay = p.split_layout()
     Wp, planes = lay["Wp"], lay["planes"]
+    used = p.panel_slices(ws)[0]        # one panel (k = M); planes beyond it are not written
+    assert 1 <= used <= planes
     raw = ws.cpu().numpy()
     esz = 2 if fmt == "bf16" else 1
     dt = np.uint16 if esz == 2 else np.uint8
@@ -106,7 +108,7 @@ def test_digit_planes_match_oracle_bitwise(prec, fmt):
     DA = split_ref.digits(A, e_ref, planes, fmt, axis=1)       # (s, m, k)
     DB = split_ref.digits(B, f_ref, planes, fmt, axis=0)       # (s, k, n)
     t = split_ref.FORMATS[fmt][1]
-    for l in range(planes):
+    for l in range(used):
         if fmt == "bf16":
             wa = _bf16_bits(np.ldexp(DA[l], -t * l))
             wb = _bf16_bits(np.ldexp(DB[l].T, -t * l))
