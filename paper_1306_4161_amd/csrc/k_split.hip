@@ -133,9 +133,61 @@ __device__ void split_stats_lines(const SplitArgs& p, int blk) {
   }
 }
 
+// A rows: the same 64-row x 16-k tiles as the digit pass (lanes along k,
+// 8 rows x 128 bytes per wave-load); partial max and sum per row, reduced
+// over the 8 lanes of a row and then over the waves.
+__device__ void split_stats_rows(const SplitArgs& p, int blk) {
+  constexpr int NW = kSplitWaves;
+  __shared__ double red_mx[NW][64], red_sm[NW][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane >> 3, kp = 2 * (lane & 7);
+  double mx[8], sm[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    mx[i] = 0.0;
+    sm[i] = 0.0;
+  }
+  for (int k0 = wave * 16; k0 < p.w; k0 += 16 * NW) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
+      const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
+      const double x0 = k0 + kp < p.w ? fabs(rp[0]) : 0.0;
+      const double x1 = k0 + kp + 1 < p.w ? fabs(rp[1]) : 0.0;
+      mx[i] = fmax(mx[i], fmax(x0, x1));
+      sm[i] += x0 + x1;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    for (int o = 1; o < 8; o <<= 1) {
+      mx[i] = fmax(mx[i], __shfl_xor(mx[i], o));
+      sm[i] += __shfl_xor(sm[i], o);
+    }
+    if ((lane & 7) == 0) {
+      red_mx[wave][lr + 8 * i] = mx[i];
+      red_sm[wave][lr + 8 * i] = sm[i];
+    }
+  }
+  __syncthreads();
+  const int row = blk * 64 + lane;
+  if (wave != 0 || row >= p.m) return;
+  double m2 = red_mx[0][lane], s2 = red_sm[0][lane];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    m2 = fmax(m2, red_mx[w][lane]);
+    s2 += red_sm[w][lane];
+  }
+  p.eA[row] = exponent_bound(m2);
+  if (s2 > 0.0) {
+    const float kap = (float)log2(m2 * (double)p.w / s2);
+    atomicMax(&p.stats[0], __float_as_uint(fmaxf(kap, 0.0f)));
+  }
+}
+
 __global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs p) {
   const int ga = (p.m + 63) / 64;
-  if ((int)blockIdx.x < ga) split_stats_lines<false>(p, blockIdx.x);
+  if ((int)blockIdx.x < ga) split_stats_rows(p, blockIdx.x);
   else split_stats_lines<true>(p, blockIdx.x - ga);
 }
 
@@ -179,12 +231,70 @@ __device__ void split_digit_lines(const SplitArgs& p, int blk, int s) {
   }
 }
 
+// A rows: each wave stages a 64-row x 16-k tile through its own LDS region
+// (read with lanes along k, 8 rows x 128 bytes per wave-load; row stride 18
+// doubles, so the per-row 16-byte reads of 16 lanes hit distinct banks),
+// then lane = row as in split_digit_lines.
+constexpr int kTileStride = 18;              // doubles per staged row
+
+template <int FMT>
+__device__ void split_digit_rows(const SplitArgs& p, int blk, int s, double* tile) {
+  constexpr int H = FMT == 0 ? 8 : 4;
+  constexpr int T = FMT == 0 ? 9 : 5;
+  constexpr int ESZ = FMT == 0 ? 2 : 1;
+  constexpr int NW = kSplitWaves;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = blk * 64 + lane;
+  const bool valid = line < p.m;
+  const int e = p.eA[valid ? line : p.m - 1];
+  uint8_t* dig = (uint8_t*)p.digA;
+  const int64_t blkel = (int64_t)p.m * 16;
+  const int lr = lane >> 3, kp = 2 * (lane & 7);   // load role: row lr + 8 i, k pair kp
+  for (int k0 = wave * 16; k0 < p.Wp; k0 += 16 * NW) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
+      const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
+      const double x0 = k0 + kp < p.w ? rp[0] : 0.0;
+      const double x1 = k0 + kp + 1 < p.w ? rp[1] : 0.0;
+      double* t = tile + (lr + 8 * i) * kTileStride + kp;
+      t[0] = x0;
+      t[1] = x1;
+    }
+    double r[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) r[q] = ldexp(tile[lane * kTileStride + q], -e);
+    if (valid) {
+      const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
+      int shift = H;
+      for (int l = 0; l < s; ++l) {
+        uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const double y = ldexp(r[q], shift);
+          const double d = rint(y);
+          r[q] = y - d;
+          if (FMT == 0)
+            w32[q >> 1] |= (__float_as_uint((float)ldexp(d, -T * l)) >> 16) << (16 * (q & 1));
+          else
+            w32[q >> 2] |= (uint32_t)e4m3_of_int((int)d) << (8 * (q & 3));
+        }
+        shift = T;
+        uint8_t* dst = dig + (l * p.planeA + pos) * ESZ;
+        ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
+        if (FMT == 0) ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
+      }
+    }
+  }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArgs p) {
+  __shared__ double tiles[kSplitWaves][64 * kTileStride];
   const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k,
                              FMT == 0 ? 8 : 4, FMT == 0 ? 9 : 5);
   const int ga = (p.m + 63) / 64;
-  if ((int)blockIdx.x < ga) split_digit_lines<FMT, false>(p, blockIdx.x, s);
+  if ((int)blockIdx.x < ga) split_digit_rows<FMT>(p, blockIdx.x, s, tiles[threadIdx.x >> 6]);
   else split_digit_lines<FMT, true>(p, blockIdx.x - ga, s);
 }
 
