@@ -85,11 +85,13 @@ __device__ __forceinline__ int panel_slices(const uint32_t* stats, int fixed_s, 
 // blocks w, w + 8, w + 16, ...  The digits of a (line, k16 block) unit are 16
 // consecutive elements of one plane (32 bytes in BF16), and consecutive
 // lines are consecutive units of the k16-block-major layout, so each wave
-// stores 64 x 32 contiguous bytes per plane.  A rows are read 16 contiguous
-// doubles per lane; B columns one 512-byte row segment per wave-load.  The
-// statistics pass writes each line's exponent and the panel's kappa; the
-// digit pass then knows the panel's slice count and writes only those
-// planes.  Both passes run over A's and B's blocks in one launch each.
+// stores 64 x 32 contiguous bytes per plane.  A rows are read as 8 rows x
+// 128 bytes per wave-load (staged through LDS in the digit pass); B columns
+// one 512-byte row segment per wave-load.  Every wave issues the loads of its
+// next 16-k tile before it works on the current one.  The statistics pass
+// writes each line's exponent and the panel's kappa; the digit pass then
+// knows the panel's slice count and writes only those planes.  Both passes
+// run over A's and B's blocks in one launch each.
 template <bool COLS>
 __device__ __forceinline__ double panel_at(const SplitArgs& p, int ln, int kk) {
   return COLS ? p.B[(int64_t)(p.k0 + kk) * p.ldb + ln] : p.A[(int64_t)ln * p.lda + p.k0 + kk];
@@ -107,14 +109,21 @@ __device__ void split_stats_lines(const SplitArgs& p, int blk) {
   const bool valid = line < nl;
   const int ln = valid ? line : nl - 1;      // clamped (loads only)
   double mx = 0.0, sm = 0.0;
-  for (int k0 = wave * 16; k0 < p.w; k0 += 16 * NW) {
-    double x[16];
+  // the next tile's loads are issued before the current tile is reduced
+  double x[16], y[16] = {};
+  auto load = [&](double* v, int k0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = k0 + q < p.w ? fabs(panel_at<COLS>(p, ln, k0 + q)) : 0.0;
+    for (int q = 0; q < 16; ++q) v[q] = k0 + q < p.w ? panel_at<COLS>(p, ln, k0 + q) : 0.0;
+  };
+  int k0 = wave * 16;
+  if (k0 < p.w) load(x, k0);
+  for (; k0 < p.w; k0 += 16 * NW) {
+    if (k0 + 16 * NW < p.w) load(y, k0 + 16 * NW);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      mx = fmax(mx, x[q]);
-      sm += x[q];
+      mx = fmax(mx, fabs(x[q]));
+      sm += fabs(x[q]);
+      x[q] = y[q];
     }
   }
   red_mx[wave][lane] = mx;
@@ -147,15 +156,28 @@ __device__ void split_stats_rows(const SplitArgs& p, int blk) {
     mx[i] = 0.0;
     sm[i] = 0.0;
   }
-  for (int k0 = wave * 16; k0 < p.w; k0 += 16 * NW) {
+  // the next tile's loads are issued before the current tile is reduced
+  double x[16], y[16] = {};
+  auto load = [&](double* v, int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
       const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
-      const double x0 = k0 + kp < p.w ? fabs(rp[0]) : 0.0;
-      const double x1 = k0 + kp + 1 < p.w ? fabs(rp[1]) : 0.0;
+      v[2 * i] = k0 + kp < p.w ? rp[0] : 0.0;
+      v[2 * i + 1] = k0 + kp + 1 < p.w ? rp[1] : 0.0;
+    }
+  };
+  int k0 = wave * 16;
+  if (k0 < p.w) load(x, k0);
+  for (; k0 < p.w; k0 += 16 * NW) {
+    if (k0 + 16 * NW < p.w) load(y, k0 + 16 * NW);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double x0 = fabs(x[2 * i]), x1 = fabs(x[2 * i + 1]);
       mx[i] = fmax(mx[i], fmax(x0, x1));
       sm[i] += x0 + x1;
+      x[2 * i] = y[2 * i];
+      x[2 * i + 1] = y[2 * i + 1];
     }
   }
 #pragma unroll
@@ -205,10 +227,19 @@ __device__ void split_digit_lines(const SplitArgs& p, int blk, int s) {
   uint8_t* dig = (uint8_t*)(COLS ? p.digB : p.digA);
   const int64_t plane = COLS ? p.planeB : p.planeA;   // elements per plane
   const int64_t blkel = (int64_t)nl * 16;              // elements per k16 block
-  for (int k0 = wave * 16; k0 < p.Wp; k0 += 16 * NW) {
+  // the next tile's loads are issued before the current tile's digits
+  double x[16];
+  auto load = [&](double* v, int k0) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = k0 + q < p.w ? panel_at<COLS>(p, line, k0 + q) : 0.0;
+  };
+  int kf = wave * 16;
+  if (kf < p.Wp) load(x, kf);
+  for (int k0 = kf; k0 < p.Wp; k0 += 16 * NW) {
     double r[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) r[q] = ldexp(k0 + q < p.w ? panel_at<COLS>(p, line, k0 + q) : 0.0, -e);
+    for (int q = 0; q < 16; ++q) r[q] = ldexp(x[q], -e);
+    if (k0 + 16 * NW < p.Wp) load(x, k0 + 16 * NW);
     const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
     int shift = H;
     for (int l = 0; l < s; ++l) {
@@ -250,20 +281,30 @@ __device__ void split_digit_rows(const SplitArgs& p, int blk, int s, double* til
   uint8_t* dig = (uint8_t*)p.digA;
   const int64_t blkel = (int64_t)p.m * 16;
   const int lr = lane >> 3, kp = 2 * (lane & 7);   // load role: row lr + 8 i, k pair kp
-  for (int k0 = wave * 16; k0 < p.Wp; k0 += 16 * NW) {
+  // the next tile's loads are issued before the current tile's digits
+  double x[16];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
       const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
-      const double x0 = k0 + kp < p.w ? rp[0] : 0.0;
-      const double x1 = k0 + kp + 1 < p.w ? rp[1] : 0.0;
+      x[2 * i] = k0 + kp < p.w ? rp[0] : 0.0;
+      x[2 * i + 1] = k0 + kp + 1 < p.w ? rp[1] : 0.0;
+    }
+  };
+  int kf = wave * 16;
+  if (kf < p.Wp) load(kf);
+  for (int k0 = kf; k0 < p.Wp; k0 += 16 * NW) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
       double* t = tile + (lr + 8 * i) * kTileStride + kp;
-      t[0] = x0;
-      t[1] = x1;
+      t[0] = x[2 * i];
+      t[1] = x[2 * i + 1];
     }
     double r[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) r[q] = ldexp(tile[lane * kTileStride + q], -e);
+    if (k0 + 16 * NW < p.Wp) load(k0 + 16 * NW);
     if (valid) {
       const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
       int shift = H;
@@ -605,7 +646,8 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
   // DMA wave-instructions per 16-k step of waves 0-1 and 2-3
   constexpr int NIHI = 3 * (S / 2) + (S & 1 ? 2 : 0), NILO = 3 * (S / 2) + (S & 1);
   constexpr int NACC = S < 5 ? S : 5;
-  constexpr int LAG = S < 3 ? S : 3;           // rows of fragment reads ahead of the MFMAs
+  // rows of fragment reads ahead of the MFMAs (2 measured best up to 5 planes, 3 above)
+  constexpr int LAG = S < 3 ? S : (S <= 5 ? 2 : 3);
   static_assert(NS >= 3 && NS * SB <= kBf16Lds, "LDS ring");
 
   const int tid = threadIdx.x, lane = tid & 63;
