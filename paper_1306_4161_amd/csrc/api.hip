@@ -262,10 +262,14 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
     a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
     a.persistent = p->opts.persistent;
     // direct-to-LDS loads move 16-byte units: every k bound, leading
-    // dimension and column offset must be even and the operands aligned
+    // dimension and column offset must be even and the operands aligned;
+    // the per-lane byte offsets (up to a tile's rows of A, 16 rows of B)
+    // must stay below 2^31
     const bool dma = !p->opts.staged && hs::fp64_has_dma(p->cfg) && p->items_even &&
                      !((k0 | k1 | p->b | lda | ldb) & 1) &&
-                     !(((uintptr_t)A | (uintptr_t)B) & 15);
+                     !(((uintptr_t)A | (uintptr_t)B) & 15) &&
+                     (int64_t)p->cfg.tm * lda * 8 < (int64_t(1) << 31) &&
+                     (int64_t)16 * ldb * 8 < (int64_t(1) << 31);
     hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream, dma);
     if (e != hipSuccess) {
       set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));

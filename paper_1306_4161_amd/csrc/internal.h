@@ -43,6 +43,10 @@ __device__ __forceinline__ void ring_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Buffer descriptor word 3 for raw (untyped) buffer loads on CDNA: data
+// format 32 bits, no swizzle, no index stride.
+constexpr int kBufferWord3 = 0x00020000;
+
 // Kernel configurations (macro-tile and k-chunk) compiled into the library.
 struct TileCfg { int tm, tn, kc; };
 const std::vector<TileCfg>& fp64_configs();

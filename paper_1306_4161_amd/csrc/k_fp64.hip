@@ -23,6 +23,8 @@
 // from uniform per-chunk base addresses.  Full chunks of full macro-tiles
 // take an unpredicated path; ragged edges (tile boundaries, the ragged last
 // inner step) a predicated one that zero-fills.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace hs {
@@ -202,7 +204,7 @@ void fp64_update_kernel(UpdateArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// Direct-to-LDS variant (gfx950 global_load_lds_dwordx4): the chunk loads go
+// Direct-to-LDS variant (buffer_load_dwordx4 ... lds): the chunk loads go
 // from global memory straight into an NS-stage LDS ring, with no staging
 // registers, so several chunks are in flight per workgroup.  Each
 // wave-instruction writes 64 consecutive 16-byte LDS units; which global
@@ -210,12 +212,17 @@ void fp64_update_kernel(UpdateArgs p) {
 //   A stage: As[row][u'] (row = 128 B = 8 units of 2 doubles),
 //            u' = u ^ ((row / 2) % 8)     -> fragment reads conflict-free
 //   B stage: Bs[k][u'] (row = TN doubles), u' = u ^ (8 (k % 2))
-// Lanes whose source is outside the item (ragged rows/cols) read a zero
-// page instead.  Used when every 16-byte unit is either wholly inside or
-// wholly outside the k-range (even k bounds, even leading dimensions, even
-// column offsets, 16-byte aligned operands); otherwise the staged kernel
+// The loads go through buffer descriptors rebased at every chunk (A at the
+// item's first row and the chunk's first column, B at the chunk's first row
+// and the item's first column), so each lane keeps one 32-bit byte offset
+// per instruction for the whole item.  Lanes whose source is outside the
+// item (ragged rows/cols, or k past a short chunk) take an offset past the
+// descriptor's range, which the hardware returns as zeros.  Used when every
+// 16-byte unit is either wholly inside or wholly outside the k-range (even k
+// bounds, even leading dimensions, even column offsets, 16-byte aligned
+// operands) and the offsets fit in 31 bits; otherwise the staged kernel
 // above runs.
-__device__ __attribute__((aligned(16))) double g_zero_page[2] = {0.0, 0.0};
+constexpr uint32_t kDmaOut = 0x80000000u;   // descriptor range; offsets >= it read zero
 
 template <int TM, int TN, int NS, int WM, int WN, int OCC>
 __global__ __launch_bounds__(WM * WN * 64, OCC)
@@ -231,7 +238,8 @@ void fp64_dma_kernel(UpdateArgs p) {
   static_assert(TN % 16 == 0 && BUPR >= 16, "B swizzle needs >= 16 units per row");
   __shared__ __attribute__((aligned(1024))) uint8_t smem[NS * SBYTES];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: LDS targets in SGPRs
   const int wm = wave / WN, wn = wave % WN;
   const int l16 = lane & 15, lq = lane >> 4;
   const int k0 = (int)p.k0, k1 = (int)p.k1, bstep = (int)p.bstep;
@@ -250,22 +258,17 @@ void fp64_dma_kernel(UpdateArgs p) {
     const double* Bb = p.B + it.c0;
     double* Cb = p.C + (int64_t)it.r0 * p.ldc + it.c0;
 
-    // Per-item DMA sources (chunk offset 0) of this wave's instructions;
-    // a chunk at k-offset c0 adds c0 doubles to A sources and c0 rows to B
-    // sources.  Lanes whose unit lies outside the item read the zero page
-    // (and do not move with the chunk).
-    const double* asrc[AINS];
-    const double* bsrc[BINS];
-    bool aok[AINS], bok[BINS];
+    // Per-item byte offsets of this wave's DMA units from the chunk's
+    // buffer bases (kDmaOut for units outside the item).
+    uint32_t aoff[AINS], boff[BINS];
     int bkk[BINS], au2[AINS];
 #pragma unroll
     for (int j = 0; j < AINS; ++j) {
       const int t = wave * AINS + j;               // 1 KB block: rows 8t .. 8t+7
       const int row = 8 * t + (lane >> 3);
       const int u = (lane & 7) ^ ((row >> 1) & 7);
-      aok[j] = row < it.h;
       au2[j] = 2 * u;
-      asrc[j] = aok[j] ? Ab + (int64_t)row * p.lda + 2 * u : g_zero_page;
+      aoff[j] = row < it.h ? (uint32_t)((int64_t)row * p.lda * 8 + 16 * u) : kDmaOut;
     }
 #pragma unroll
     for (int j = 0; j < BINS; ++j) {
@@ -273,31 +276,36 @@ void fp64_dma_kernel(UpdateArgs p) {
       const int unit = t * 64 + lane;              // LDS unit in the stage
       const int kk = unit / BUPR, us = unit % BUPR;
       const int u = us ^ (8 * (kk & 1));
-      bok[j] = 2 * u < it.w;
       bkk[j] = kk;
-      bsrc[j] = bok[j] ? Bb + (int64_t)kk * p.ldb + 2 * u : g_zero_page;
+      boff[j] = 2 * u < it.w ? (uint32_t)((int64_t)kk * p.ldb * 8 + 16 * u) : kDmaOut;
     }
     // issue the DMA loads of chunk [c0, c0 + clen) into ring stage `st`
     auto issue = [&](int c0, int clen, int st) {
       uint8_t* sA = smem + st * SBYTES;
       uint8_t* sB = sA + ABYTES;
-      const int64_t boffs = (int64_t)c0 * p.ldb;
+      const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(Ab + c0), (short)0, (int)kDmaOut, kBufferWord3);
+      const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(Bb + (int64_t)c0 * p.ldb), (short)0, (int)kDmaOut, kBufferWord3);
+      // a short chunk (a step's ragged end) also zeroes the units past clen
+      auto put = [&](auto shortc) {
 #pragma unroll
-      for (int j = 0; j < AINS; ++j) {
-        const double* src = asrc[j];
-        if (aok[j]) src += c0;
-        if (clen < KC && au2[j] >= clen) src = g_zero_page;
-        __builtin_amdgcn_global_load_lds((const void*)src,
-            (__attribute__((address_space(3))) void*)(sA + (wave * AINS + j) * 1024), 16, 0, 0);
-      }
+        for (int j = 0; j < AINS; ++j) {
+          const uint32_t off = shortc && au2[j] >= clen ? kDmaOut : aoff[j];
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              ra, (__attribute__((address_space(3))) void*)(sA + (wave * AINS + j) * 1024), 16,
+              off, 0, 0, 0);
+        }
 #pragma unroll
-      for (int j = 0; j < BINS; ++j) {
-        const double* src = bsrc[j];
-        if (bok[j]) src += boffs;
-        if (clen < KC && bkk[j] >= clen) src = g_zero_page;
-        __builtin_amdgcn_global_load_lds((const void*)src,
-            (__attribute__((address_space(3))) void*)(sB + (wave * BINS + j) * 1024), 16, 0, 0);
-      }
+        for (int j = 0; j < BINS; ++j) {
+          const uint32_t off = shortc && bkk[j] >= clen ? kDmaOut : boff[j];
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rb, (__attribute__((address_space(3))) void*)(sB + (wave * BINS + j) * 1024), 16,
+              off, 0, 0, 0);
+        }
+      };
+      if (clen < KC) put(std::true_type{});
+      else put(std::false_type{});
     };
 
     d4 acc[FM][FN];

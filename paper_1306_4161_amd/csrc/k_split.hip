@@ -609,9 +609,6 @@ void slice_update_kernel(SliceArgs p) {
 // The slice count S is a template parameter of the item loop (the kernel
 // dispatches on the panel's count once), so the pair structure is static.
 constexpr int kBf16TM = 64, kBf16TN = 128, kBf16NW = 4;
-// Buffer descriptor word 3 for raw (untyped) buffer loads on CDNA: data
-// format 32 bits, no swizzle, no index stride.
-constexpr int kBufferWord3 = 0x00020000;
 constexpr int kBf16Lds = 152 * 1024;  // LDS ring budget (bytes)
 // ring depth for S planes: as many 16-k stages as fit, at most 5
 constexpr int bf16_stages(int S) {
