@@ -86,7 +86,8 @@ typedef struct {
   int32_t tau_bits;   /* split forms, per-panel slice choice: the smallest s    */
                       /* whose modelled max error relative to (|A||B|)_ij is    */
                       /* <= 2^-tau_bits (model: bits(s) against the panel's     */
-                      /* value spread and k); 0 => 48                           */
+                      /* value spread and k; max_slices when the spread         */
+                      /* statistic is saturated by a narrow panel); 0 => 48     */
   int32_t staged;     /* FP64 path: 1 = always the register-staged kernel,      */
                       /* 0 = direct-to-LDS loads where alignment allows         */
   int32_t reserved[4];

@@ -302,6 +302,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   sa.smax = p->opts.max_slices;
   sa.fixed_s = p->opts.slices; sa.smin = p->opts.min_slices; sa.tau_bits = p->opts.tau_bits;
   sa.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
+  sa.log2w = (float)std::log2((double)std::max<int64_t>(1, k1 - k0));
   sa.digA = w8 + p->off_digA; sa.planeA = (int64_t)p->m * sa.Wp;
   sa.digB = w8 + p->off_digB; sa.planeB = (int64_t)p->n * sa.Wp;
   sa.eA = (int32_t*)(w8 + p->off_eA); sa.fB = (int32_t*)(w8 + p->off_fB);
@@ -329,6 +330,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   la.fixed_s = p->opts.slices; la.smin = p->opts.min_slices; la.smax = p->opts.max_slices;
   la.tau_bits = p->opts.tau_bits;
   la.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
+  la.log2w = sa.log2w;
   la.zero_init = zero_init; la.persistent = persistent ? 1 : 0;
   e = hs::launch_slices(p->fmt, la, grid, stream);
   if (e != hipSuccess) {

@@ -67,14 +67,21 @@ __device__ inline uint8_t e4m3_of_int(int d) {
 // add with random signs over k, (|A||B|)_ij grows like k); bits(s) =
 // H + T (s - 1).  The smallest s whose estimate is within 2^-tau is taken
 // (or the fixed count), clamped to [smin, smax] and to the planes stored.
+// kappa cannot exceed the panel width w, so when ka or kb comes within one
+// bit of log2 w the statistic no longer measures the spread (narrow panels,
+// or lines dominated by one element): such a panel takes smax.
 // The split's digit pass and the product kernels evaluate it identically.
 __device__ __forceinline__ int panel_slices(const uint32_t* stats, int fixed_s, int smin, int smax,
-                                            int tau_bits, float log2k, int H, int T) {
+                                            int tau_bits, float log2k, float log2w, int H, int T) {
   int s = fixed_s;
   if (s <= 0) {
     const float ka = __uint_as_float(stats[0]), kb = __uint_as_float(stats[1]);
-    const float need = (float)tau_bits + 0.75f * (ka + kb) + 1.0f - 0.5f * log2k;
-    s = (int)ceilf((need - (float)H) / (float)T) + 1;
+    if (fmaxf(ka, kb) >= log2w - 1.0f) {
+      s = smax;
+    } else {
+      const float need = (float)tau_bits + 0.75f * (ka + kb) + 1.0f - 0.5f * log2k;
+      s = (int)ceilf((need - (float)H) / (float)T) + 1;
+    }
     s = max(smin, min(smax, s));
   }
   return max(1, min(kSplitMaxSlices, s));
@@ -332,7 +339,7 @@ __device__ void split_digit_rows(const SplitArgs& p, int blk, int s, double* til
 template <int FMT>
 __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArgs p) {
   __shared__ double tiles[kSplitWaves][64 * kTileStride];
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k,
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w,
                              FMT == 0 ? 8 : 4, FMT == 0 ? 9 : 5);
   const int ga = (p.m + 63) / 64;
   if ((int)blockIdx.x < ga) split_digit_rows<FMT>(p, blockIdx.x, s, tiles[threadIdx.x >> 6]);
@@ -377,7 +384,7 @@ void slice_update_kernel(SliceArgs p) {
   const int l16 = lane & 15, lq = lane >> 4;
 
   // slice count of this panel: fixed, or from the split's exponent statistics
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, H, TB);
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w, H, TB);
   if (blockIdx.x == 0 && tid == 0 && p.slices_out) *p.slices_out = s;
 
   const int bid = blockIdx.x;
@@ -869,7 +876,7 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
 
 __global__ __launch_bounds__(256, 1) void slice_bf16_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, 8, 9);
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w, 8, 9);
   if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
   switch (s) {
     case 1: slice_bf16_items<1>(p, smem); break;

@@ -19,7 +19,7 @@ struct SplitArgs {
   int32_t* eA; int32_t* fB;          // per-row / per-column exponents
   uint32_t* stats;                   // [0]: max log2 kappa over A rows, [1]: over B cols
   int32_t fixed_s, smin, tau_bits;   // slice-count choice (as in SliceArgs)
-  float log2k;
+  float log2k, log2w;
 };
 
 struct SliceArgs {
@@ -33,6 +33,7 @@ struct SliceArgs {
   int32_t Wp, nchunks;
   int32_t fixed_s, smin, smax, tau_bits;
   float log2k;                       // log2 of the product's inner dimension k
+  float log2w;                       // log2 of the panel width
   int32_t zero_init, persistent;
 };
 

@@ -215,3 +215,69 @@ def test_c2_shape_bf16_sampled():
     err = np.abs(C[rows, cols] - c) / s
     _say("  slices %r max scaled err %.3g" % (sorted(set(p.panel_slices(ws))), err.max()))
     assert err.max() <= GATE
+
+
+# ------------------------------------------------- edges and batching form --
+
+@pytest.mark.parametrize("shape", [
+    # m, k, n, P, Q, G, b, M
+    (1, 1, 1, 1, 1, 1, 1, 1),
+    (1, 300, 7, 1, 1, 1, 100, 300),
+    (65, 17, 129, 1, 2, 2, 17, 17),
+    (3, 1000, 2, 1, 1, 1, 250, 500),
+    (200, 64, 1, 2, 1, 2, 64, 64),
+    (96, 2, 96, 1, 1, 1, 2, 2),
+    (96, 33, 96, 1, 1, 1, 33, 33),
+])
+def test_degenerate_shapes_meet_gate(shape):
+    # exponent-spread entries on narrow panels: the per-line spread statistic
+    # saturates at the panel width there, and the slice choice must still
+    # meet the gate
+    m, k, n, P, Q, G, b, M = shape
+    _say("case split degenerate %r" % (shape,))
+    A = inputs.exponent_spread(m, k, 121, 2.0)
+    B = inputs.exponent_spread(k, n, 122, 2.0)
+    p = hs.Plan(n, P, Q, G, b, M, m=m, k=k, prec=hs.SPLIT_BF16)
+    C, ws = _run(p, A, B)
+    rows, cols = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    rows, cols = rows.ravel(), cols.ravel()
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / np.where(s > 0, s, 1.0)
+    slices = p.panel_slices(ws)
+    _say("  slices %r max scaled err %.3g" % (slices, err.max()))
+    assert all(3 <= x <= 7 for x in slices)
+    assert err.max() <= GATE
+
+
+def test_c3_block_cyclic_split_bf16_graph():
+    import torch
+    _say("case c3 split-bf16: n=10000 6x10 block-cyclic b=128 persistent+graph")
+    n = 10000
+    A = inputs.uniform(n, n, inputs.SEED_A)
+    B = inputs.uniform(n, n, inputs.SEED_B)
+    p = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=hs.SPLIT_BF16,
+                persistent=1, use_graph=1)
+    ws = p.workspace()
+    dA, dB = dev(A), dev(B)
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    outs = []
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            C.fill_(float("nan"))
+            p.run(dA, dB, C, ws=ws, stream=stream)
+        stream.synchronize()
+        outs.append(host(C))
+        dA.add_(0.0)  # eager work between replays
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    Cn = outs[0]
+    edges = list(range(0, n, 128))
+    rows, cols = inputs.sample_entries(n, n, 2048, inputs.SEED_SAMPLE, edges, edges, per_edge=2)
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(Cn[rows, cols] - c) / s
+    _say("  slices %r max scaled err %.3g" % (sorted(set(p.panel_slices(ws))), err.max()))
+    assert err.max() <= GATE
+    check_freivalds(A, B, Cn)
+    # the launch without the graph gives the same bits
+    q = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=hs.SPLIT_BF16)
+    assert np.array_equal(_run(q, dA, dB)[0], Cn)
