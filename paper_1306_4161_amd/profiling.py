@@ -7,6 +7,10 @@ the text summaries made from rocprofv3's CSV output.
     # summary file read back by bench.py (HBM bytes per launch)
     python3 -m paper_1306_4161_amd.profiling traffic --fetch OUT/f_counter_collection.csv \\
         --write OUT2/w_counter_collection.csv --kernel fp64_dma_kernel ...
+    # MFMA-busy fraction and clock from a counter pass
+    rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE --output-format csv -d OUT -o m -- \\
+        python3 -m paper_1306_4161_amd.profiling launches --path fp64
+    python3 -m paper_1306_4161_amd.profiling mfma OUT/m_counter_collection.csv --kernel fp64_dma_kernel ...
     # per-kernel time table from `rocprofv3 --kernel-trace --stats`
     python3 -m paper_1306_4161_amd.profiling stats OUT/kt_kernel_stats.csv --command "..."
 
@@ -131,6 +135,55 @@ def traffic(args):
     print(text, end="")
 
 
+def mfma(args):
+    """MFMA-busy fraction and effective clock per dispatch of one kernel.
+
+    GRBM_GUI_ACTIVE counts busy cycles of each XCD, summed over the XCDs;
+    SQ_VALU_MFMA_BUSY_CYCLES counts cycles in which a SIMD's matrix core is
+    busy, summed over every SIMD.  busy = MFMA cycles / (XCD cycles x SIMDs);
+    clock = XCD cycles / dispatch duration.
+    """
+    rows = collections.defaultdict(lambda: collections.defaultdict(float))
+    span = {}
+    names = {}
+    with open(args.csv) as f:
+        for r in csv.DictReader(f):
+            did = int(r["Dispatch_Id"])
+            rows[did][r["Counter_Name"]] += float(r["Counter_Value"])
+            span[did] = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+            names[did] = r["Kernel_Name"]
+    sel = [d for d in sorted(rows) if args.kernel in names[d]]
+    if not sel:
+        raise SystemExit("no dispatch of %r" % args.kernel)
+    lines = ["# MFMA busy fraction and clock of %s, workload %s" % (args.kernel, args.workload),
+             "# command: %s" % args.command,
+             "# summary command: python3 -m paper_1306_4161_amd.profiling %s" % shlex.join(
+                 sys.argv[1:]),
+             "# busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / xcds x simds); "
+             "clock = GRBM_GUI_ACTIVE / xcds / duration",
+             "kernel: %s" % args.kernel,
+             "source_hash: %s" % source_hash(*args.source.split(",")),
+             "xcds: %d" % args.xcds, "simds: %d" % args.simds,
+             "%-10s %12s %10s %10s" % ("dispatch", "duration_us", "clock_ghz", "mfma_busy")]
+    busy_all, clk_all = [], []
+    for d in sel:
+        v = rows[d]
+        cyc = v["GRBM_GUI_ACTIVE"] / args.xcds
+        dur = (span[d][1] - span[d][0]) * 1e-9
+        busy = v["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * args.simds)
+        clk = cyc / dur / 1e9
+        busy_all.append(busy)
+        clk_all.append(clk)
+        lines.append("%-10d %12.1f %10.3f %10.4f" % (d, dur * 1e6, clk, busy))
+    lines.append("mean_mfma_busy: %.4f" % _mean(busy_all))
+    lines.append("mean_clock_ghz: %.3f" % _mean(clk_all))
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
 def stats(args):
     with open(args.csv) as f:
         rows = list(csv.DictReader(f))
@@ -171,13 +224,22 @@ def main():
     t.add_argument("--fetch-command", default="")
     t.add_argument("--write-command", default="")
     t.add_argument("--out", default="")
+    m = sub.add_parser("mfma")
+    m.add_argument("csv")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--workload", required=True)
+    m.add_argument("--source", required=True, help="comma-separated csrc files")
+    m.add_argument("--command", default="")
+    m.add_argument("--xcds", type=int, default=8)
+    m.add_argument("--simds", type=int, default=1024)
+    m.add_argument("--out", default="")
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--command", default="")
     s.add_argument("--top", type=int, default=12)
     s.add_argument("--out", default="")
     args = ap.parse_args()
-    {"launches": launches, "traffic": traffic, "stats": stats}[args.cmd](args)
+    {"launches": launches, "traffic": traffic, "mfma": mfma, "stats": stats}[args.cmd](args)
 
 
 if __name__ == "__main__":
