@@ -587,7 +587,8 @@ void slice_update_kernel(SliceArgs p) {
 // each (two 32x32 blocks sharing the A fragment), on
 // v_mfma_f32_32x32x16_bf16.  Per 16-k step the digits of every plane of the
 // tile stream from global memory straight into an NS-stage LDS ring
-// (global_load_lds_dwordx4, 6 S wave-instructions per step over the 4 waves).
+// (buffer_load_dwordx4 ... lds through one buffer descriptor per operand,
+// 6 S wave-instructions per step over the 4 waves).
 // LDS image of one plane: [row][half] 16-byte units, the half index
 // XOR-swizzled by bit 3 of the row so that a fragment read (32 rows x one
 // half) is bank-conflict free.
@@ -598,9 +599,9 @@ void slice_update_kernel(SliceArgs p) {
 //
 // Pairs (l1, l2), l1 + l2 < S, run in S rows; row r pairs A fragment
 // S-1-r with B fragments 0 .. r, so every row needs one new fragment of each
-// operand.  Fragment reads run three rows ahead of the MFMAs (one wave per
+// operand.  Fragment reads run LAG rows ahead of the MFMAs (one wave per
 // SIMD has no other wave to hide LDS latency behind).  The step's one
-// barrier sits three rows before its end: every read of the current stage
+// barrier sits LAG rows before its end: every read of the current stage
 // has retired, so the stage is refilled by DMA for the step NS ahead (each
 // load has NS - 1 steps to land), and the next stage is complete, so its
 // first rows are read into the second register set while the step ends.
@@ -608,10 +609,11 @@ void slice_update_kernel(SliceArgs p) {
 // Level accumulators (FP32): index a = l1 + l2 (0-based) for a <= 3, one
 // shared accumulator for a >= 4.  Exact while a level's partial sums stay
 // within 2^24: a level of a + 1 pairs of |d d'| <= 2^16 may run 256/(a+1) k.
-// Every accumulator is added into the FP64 panel sum after each group of
-// four steps (64 k; the panel is padded to a multiple of 64) and restarts
-// from a zero C operand, so levels 0-3 stay exact; the shared deep
-// accumulator (weight <= 2^-36) needs no exactness.
+// Each accumulator is added into the FP64 panel sum at its own cadence
+// (levels 0, 1 and the shared one every 8 steps, levels 2 and 3 every 4;
+// the panel is padded to a multiple of 64) and restarts from a zero C
+// operand, so levels 0-3 stay exact; the shared deep accumulator (weight
+// <= 2^-36) needs no exactness.
 //
 // The slice count S is a template parameter of the item loop (the kernel
 // dispatches on the panel's count once), so the pair structure is static.
