@@ -101,8 +101,9 @@ void hsumma_opts_default(hsumma_opts* o);
  * P x Q grid (P <= m, Q <= n), G groups (Sec. III: G = I*J with I | P and
  * J | Q; the most square arrangement is chosen), inner block b >= 1, outer
  * block M with b <= M (Sec. III) and M a multiple of b.  G = 1 or G = P*Q is
- * plain SUMMA (Sec. III).  Host only: validates, builds the step schedule
- * and the work-item table.  Returns HSUMMA_ERR_INVALID on bad input.
+ * plain SUMMA (Sec. III).  m, n and k must be below 2^31.  Host only:
+ * validates, builds the step schedule and the work-item table.  Returns
+ * HSUMMA_ERR_INVALID on bad input.
  */
 int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G,
                 int64_t b, int64_t M, const hsumma_opts* opts);
@@ -110,7 +111,8 @@ void hsumma_plan_destroy(hsumma_plan_t plan);
 
 /* Queries (host only). */
 int hsumma_workspace_size(hsumma_plan_t plan, size_t* bytes);
-int hsumma_num_steps(hsumma_plan_t plan, int64_t* steps);          /* inner steps: ceil(k/b) if M|... */
+int hsumma_num_steps(hsumma_plan_t plan, int64_t* steps);          /* inner steps: sum over outer
+                                                                      blocks of ceil(width/b) */
 int hsumma_num_outer_steps(hsumma_plan_t plan, int64_t* steps);    /* ceil(k/M) */
 int hsumma_groups(hsumma_plan_t plan, int32_t* I, int32_t* J);
 int hsumma_tile_shape(hsumma_plan_t plan, int32_t pr, int32_t pc,

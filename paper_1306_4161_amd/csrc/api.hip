@@ -373,7 +373,8 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   const int64_t m = o.m ? o.m : n;
   const int64_t k = o.k ? o.k : n;
   if (n < 1 || m < 1 || k < 0 || o.m < 0 || o.k < 0) return invalid("matrix sizes must be positive");
-  if (m >= (1LL << 31) || n >= (1LL << 31)) return invalid("m and n must be below 2^31");
+  if (m >= (1LL << 31) || n >= (1LL << 31) || k >= (1LL << 31))
+    return invalid("m, n and k must be below 2^31");
   if (P < 1 || Q < 1) return invalid("P and Q must be >= 1");
   if (P > m || Q > n) return invalid("grid larger than the matrix (need P <= m, Q <= n)");
   if (G < 1) return invalid("G must be >= 1");
@@ -432,10 +433,6 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     if (p->fmt == 1 && M > 8192) {
       delete p;
       return invalid("FP8 split form needs M <= 8192 (exact FP32 accumulation over a panel)");
-    }
-    if (m >= (1LL << 31) / 1 || n >= (1LL << 31)) {
-      delete p;
-      return invalid("matrix too large for the split form");
     }
     const int64_t pad = p->fmt == 0 ? 64 : hs::kSplitChunk;   // BF16 steps in groups of 64 k
     const int64_t Wp = (M + pad - 1) / pad * pad;

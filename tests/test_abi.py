@@ -55,6 +55,14 @@ def test_plan_rejects_invalid(args, msg):
     assert msg in str(ei.value)
 
 
+def test_plan_rejects_sizes_beyond_32_bits():
+    for kw in (dict(k=2 ** 31), dict(m=2 ** 31)):
+        with pytest.raises(hs.HsummaError) as ei:
+            hs.Plan(64, 1, 1, 1, 8, 8, **kw)
+        assert ei.value.code == hs.ERR_INVALID
+        assert "below 2^31" in str(ei.value)
+
+
 def test_plan_rejects_unknown_tile_and_enum():
     with pytest.raises(hs.HsummaError):
         hs.Plan(256, 2, 2, 1, 32, tile_m=96, tile_n=96)
