@@ -197,6 +197,63 @@ int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k
                             void* stream);
 
 /*
+ * Communication-cost model of the distributed algorithm (Sec. IV) and the
+ * choice of G it implies.  Host only (no device work, no allocation).
+ *
+ * Hockney's model: one message of m elements between two processes costs
+ * alpha + m beta; gamma is the time of one floating-point operation on one
+ * process.  Broadcasts of m elements among q processes (Sec. IV):
+ *   HSUMMA_BCAST_BINOMIAL      log2(q) (alpha + m beta)
+ *   HSUMMA_BCAST_VAN_DE_GEIJN  (log2(q) + q - 1) alpha + 2 (q - 1)/q m beta
+ * On a P x Q grid with G = I x J groups (the plan's most square
+ * arrangement), n x n matrices, inner block b and outer block B: every inner
+ * step broadcasts A's pivot block (n b / P elements per process) along a
+ * process row inside the group (Q / J processes) and B's (n b / Q) along a
+ * process column (P / I); every outer step does the same between groups (J
+ * and I groups) with B.  For P = Q = sqrt(p) and I = J = sqrt(G) these are
+ * the costs of Sec. IV-A/IV-B and Tables I-II (eq. (2)-(5) when b = B); G = 1
+ * (or G = P Q with b = B) is SUMMA.  Message sizes are in elements.
+ */
+typedef enum { HSUMMA_BCAST_BINOMIAL = 0, HSUMMA_BCAST_VAN_DE_GEIJN = 1 } hsumma_bcast;
+
+typedef struct {
+  double alpha;   /* seconds per message (latency)                              */
+  double beta;    /* seconds per matrix element (reciprocal bandwidth)          */
+  double gamma;   /* seconds per floating-point operation on one process        */
+} hsumma_platform;
+
+typedef struct {
+  double comp;             /* 2 n^3 / (P Q) operations x gamma (Tables I-II)      */
+  double latency_inner;    /* alpha terms of the broadcasts inside groups         */
+  double latency_outer;    /* alpha terms of the broadcasts between groups        */
+  double bandwidth_inner;  /* beta terms inside groups                            */
+  double bandwidth_outer;  /* beta terms between groups                           */
+  double comm;             /* the four terms added                                */
+  double total;            /* comp + comm (no overlap, as in the paper)           */
+} hsumma_cost;
+
+/* Time of one broadcast of m elements among q >= 1 processes. */
+int hsumma_model_bcast(int32_t algo, const hsumma_platform* pf, double m, double q,
+                       double* seconds);
+/* Cost of C = A x B (n x n) on a P x Q grid with G groups.  Returns
+ * HSUMMA_ERR_INVALID if G cannot be arranged as I x J with I | P, J | Q, or
+ * if a size is not positive or b > B. */
+int hsumma_model_cost(int32_t algo, const hsumma_platform* pf, int64_t n, int32_t P, int32_t Q,
+                      int32_t G, int64_t b, int64_t B, hsumma_cost* out);
+/* Eq. (10): derivative in G of the Van de Geijn cost (square grid of p
+ * processes, b = B); zero at G = sqrt(p), and G = sqrt(p) is the minimum in
+ * (1, p) iff alpha / beta > 2 n b / p (eq. (11)). */
+int hsumma_model_dcomm_dgroups(const hsumma_platform* pf, int64_t n, double p, double G,
+                               int64_t b, double* derivative);
+/* The G with the least modelled communication time over every group count
+ * that the P x Q grid can arrange (costs within a relative 1e-12 of the
+ * least go to the smaller G), its cost, and the cost of SUMMA (G = 1).  Any
+ * output pointer may be null. */
+int hsumma_model_select_groups(int32_t algo, const hsumma_platform* pf, int64_t n, int32_t P,
+                               int32_t Q, int64_t b, int64_t B, int32_t* G_best,
+                               hsumma_cost* best, hsumma_cost* summa);
+
+/*
  * Learned cost model (the tuner's learned form): a 3-layer FP32 MLP
  *   Z = relu(relu(X W1 + b1) W2 + b2) W3 + b3
  * with X: N x F features per problem shape, H hidden units, and one output

@@ -23,6 +23,25 @@ namespace hs {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// Most square I x J = G with I | P, J | Q; ties to the smaller I.
+bool factor_groups(int P, int Q, int G, int* I, int* J) {
+  bool found = false;
+  double best_ratio = 0;
+  for (int i = 1; i <= P; ++i) {
+    if (P % i || G % i) continue;
+    int j = G / i;
+    if (j > Q || Q % j) continue;
+    double ratio = (double)std::max(i, j) / (double)std::min(i, j);
+    if (!found || ratio < best_ratio) {
+      found = true;
+      best_ratio = ratio;
+      *I = i;
+      *J = j;
+    }
+  }
+  return found;
+}
+
 }  // namespace hs
 
 using hs::set_error;
@@ -86,25 +105,6 @@ namespace {
 int invalid(const std::string& msg) {
   set_error(msg);
   return HSUMMA_ERR_INVALID;
-}
-
-// Most square I x J = G with I | P, J | Q; ties to the smaller I.
-bool factor_groups(int P, int Q, int G, int* I, int* J) {
-  bool found = false;
-  double best_ratio = 0;
-  for (int i = 1; i <= P; ++i) {
-    if (P % i || G % i) continue;
-    int j = G / i;
-    if (j > Q || Q % j) continue;
-    double ratio = (double)std::max(i, j) / (double)std::min(i, j);
-    if (!found || ratio < best_ratio) {
-      found = true;
-      best_ratio = ratio;
-      *I = i;
-      *J = j;
-    }
-  }
-  return found;
 }
 
 // Boundaries of a balanced block split of [0, len) into parts.
@@ -387,7 +387,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     return invalid("unknown precision");
   if (o.nb < 0) return invalid("nb must be >= 0");
   int I = 0, J = 0;
-  if (!factor_groups(P, Q, G, &I, &J))
+  if (!hs::factor_groups(P, Q, G, &I, &J))
     return invalid("G cannot be arranged as I x J groups with I | P and J | Q");
 
   hsumma_plan_s* p = new (std::nothrow) hsumma_plan_s();

@@ -62,5 +62,7 @@ struct SplitArgs;
 struct SliceArgs;
 
 void set_error(const std::string& msg);
+// Most square I x J = G with I | P and J | Q (ties to the smaller I).
+bool factor_groups(int P, int Q, int G, int* I, int* J);
 
 }  // namespace hs

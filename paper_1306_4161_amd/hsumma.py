@@ -23,8 +23,24 @@ EXPORTED = [
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
     "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
     "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
-    "hsumma_mlp_adam",
+    "hsumma_mlp_adam", "hsumma_model_bcast", "hsumma_model_cost", "hsumma_model_dcomm_dgroups",
+    "hsumma_model_select_groups",
 ]
+
+BCAST_BINOMIAL, BCAST_VAN_DE_GEIJN = 0, 1
+
+
+class Platform(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class Cost(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in (
+        "comp", "latency_inner", "latency_outer", "bandwidth_inner", "bandwidth_outer", "comm",
+        "total")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Opts(ctypes.Structure):
@@ -91,6 +107,12 @@ def lib():
         L.hsumma_mlp_grad.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.hsumma_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, i32, vp]
+        dbl = ctypes.c_double
+        L.hsumma_model_bcast.argtypes = [i32, P(Platform), dbl, dbl, P(dbl)]
+        L.hsumma_model_cost.argtypes = [i32, P(Platform), i64, i32, i32, i32, i64, i64, P(Cost)]
+        L.hsumma_model_dcomm_dgroups.argtypes = [P(Platform), i64, dbl, dbl, i64, P(dbl)]
+        L.hsumma_model_select_groups.argtypes = [i32, P(Platform), i64, i32, i32, i64, i64, P(i32),
+                                                 P(Cost), P(Cost)]
         L.hsumma_last_error.restype = ctypes.c_char_p
         L.hsumma_last_error.argtypes = []
         L.hsumma_version.restype = ctypes.c_char_p
@@ -331,3 +353,40 @@ def mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-
 
 def version():
     return lib().hsumma_version().decode()
+
+
+# -- communication-cost model (host only) ---------------------------------------
+
+def model_bcast(algo, alpha, beta, m, q):
+    """Seconds for one broadcast of m elements among q processes."""
+    out = ctypes.c_double()
+    pf = Platform(alpha, beta, 0.0)
+    _check(lib().hsumma_model_bcast(algo, ctypes.byref(pf), float(m), float(q), ctypes.byref(out)))
+    return out.value
+
+
+def model_cost(algo, alpha, beta, gamma, n, P, Q, G, b, B):
+    """Modelled cost (seconds) of C = A x B, n x n, on a P x Q grid with G groups."""
+    c = Cost()
+    pf = Platform(alpha, beta, gamma)
+    _check(lib().hsumma_model_cost(algo, ctypes.byref(pf), n, P, Q, G, b, B, ctypes.byref(c)))
+    return c.as_dict()
+
+
+def model_dcomm_dgroups(alpha, beta, n, p, G, b):
+    """Eq. (10): d(communication)/dG, Van de Geijn broadcasts, square grid, b = B."""
+    out = ctypes.c_double()
+    pf = Platform(alpha, beta, 0.0)
+    _check(lib().hsumma_model_dcomm_dgroups(ctypes.byref(pf), n, float(p), float(G), b,
+                                            ctypes.byref(out)))
+    return out.value
+
+
+def model_select_groups(algo, alpha, beta, gamma, n, P, Q, b, B):
+    """(G with the least modelled communication, its cost, SUMMA's cost)."""
+    g = ctypes.c_int32()
+    best, summa = Cost(), Cost()
+    pf = Platform(alpha, beta, gamma)
+    _check(lib().hsumma_model_select_groups(algo, ctypes.byref(pf), n, P, Q, b, B, ctypes.byref(g),
+                                            ctypes.byref(best), ctypes.byref(summa)))
+    return g.value, best.as_dict(), summa.as_dict()

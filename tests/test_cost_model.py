@@ -1,0 +1,138 @@
+"""Parity of the library's communication-cost model (hsumma_model_*, host
+only) with the oracle of Sec. IV (oracle/cost_model.py).
+
+The two are written independently: the library evaluates the non-square
+grid form once, the oracle prints the paper's square closed forms (Tables
+I-II, eq. (2)-(5), (10), (12)) and its own non-square reading.  They agree
+to rounding (relative 1e-12).  The choice of G is checked against a brute
+force over every arrangeable group count in the oracle, and against the
+paper's statement that G = sqrt(p) is the optimum when alpha/beta exceeds
+2 n b / p (eq. (11)).
+"""
+import math
+
+import pytest
+
+from oracle import cost_model as cm
+from oracle import plan_ref
+from paper_1306_4161_amd import hsumma as hs
+
+VDG, BIN = hs.BCAST_VAN_DE_GEIJN, hs.BCAST_BINOMIAL
+ALGOS = [(VDG, cm.L_vdg, cm.W_vdg, cm.hsumma_vdg, cm.summa_vdg),
+         (BIN, cm.L_binomial, cm.W_binomial, cm.hsumma_binomial, cm.summa_binomial)]
+PLATFORMS = {   # the paper's parameter sets, read as in tests/test_cost_model_ref.py
+    "grid5000": dict(n=8192, P=8, Q=16, b=64, alpha=1e-4, beta=1e-9),
+    "bgp": dict(n=65536, P=128, Q=128, b=256, alpha=3e-6, beta=1e-9),
+    "exascale": dict(n=2 ** 22, P=1024, Q=1024, b=256, alpha=5e-7, beta=1e-11),
+}
+
+
+def close(a, b, rel=1e-12):
+    return abs(a - b) <= rel * max(abs(a), abs(b), 1e-300)
+
+
+def test_broadcast_matches_oracle():
+    for q in (1, 2, 3, 16, 128, 1000):
+        for m in (0.0, 1.0, 4096.0, 1e7):
+            assert close(hs.model_bcast(BIN, 2e-6, 1e-9, m, q), cm.bcast_binomial(m, q, 2e-6, 1e-9))
+            assert close(hs.model_bcast(VDG, 2e-6, 1e-9, m, q), cm.bcast_vdg(m, q, 2e-6, 1e-9))
+
+
+@pytest.mark.parametrize("sp,sg,b,B", [(16, 4, 64, 64), (16, 4, 64, 256), (128, 8, 256, 256),
+                                       (128, 16, 128, 1024), (32, 1, 64, 64), (32, 32, 64, 64),
+                                       (64, 2, 32, 96)])
+def test_square_grid_matches_tables(sp, sg, b, B):
+    n, p, G = 16384, sp * sp, sg * sg
+    al, be, ga = 3e-6, 1e-9, 2.5e-12
+    for algo, _, _, hsumma, _ in ALGOS:
+        c = hs.model_cost(algo, al, be, ga, n, sp, sp, G, b, B)
+        li, lo, bi, bo = hsumma(n, p, G, b, B, al, be)
+        assert close(c["latency_inner"], li) and close(c["latency_outer"], lo)
+        assert close(c["bandwidth_inner"], bi) and close(c["bandwidth_outer"], bo)
+        assert close(c["comm"], li + lo + bi + bo)
+        assert close(c["comp"], 2 * n ** 3 / p * ga) and close(c["total"], c["comp"] + c["comm"])
+
+
+@pytest.mark.parametrize("name", sorted(PLATFORMS))
+def test_summa_and_general_model(name):
+    pf = PLATFORMS[name]
+    n, P, b, al, be = pf["n"], pf["P"], pf["b"], pf["alpha"], pf["beta"]
+    if pf["P"] != pf["Q"]:
+        pytest.skip("the paper's closed forms are for square grids")
+    p = P * P
+    for algo, L, W, _, summa in ALGOS:
+        c1 = hs.model_cost(algo, al, be, 0.0, n, P, P, 1, b, b)
+        assert close(c1["comm"], sum(summa(n, p, b, al, be)))
+        assert close(c1["comm"], cm.T_S(n, p, b, L, W, al, be))
+        # square groups (sqrt(G) x sqrt(G)), the case eq. (3)-(5) describe
+        for sg in (2, 4, 8, 16):
+            cg = hs.model_cost(algo, al, be, 0.0, n, P, P, sg * sg, b, b)
+            assert close(cg["comm"], cm.T_HS(n, p, sg * sg, b, L, W, al, be))
+    q = round(p ** 0.25)
+    if q ** 4 == p:   # eq. (12) needs sqrt(p) = q x q groups
+        assert close(hs.model_cost(VDG, al, be, 0.0, n, P, P, q * q, b, b)["comm"],
+                     cm.optimal_vdg(n, p, b, al, be), rel=1e-11)
+
+
+@pytest.mark.parametrize("P,Q,G,b,B", [(8, 16, 4, 64, 64), (6, 10, 15, 128, 128),
+                                       (4, 16, 8, 32, 256), (12, 8, 6, 100, 300), (3, 5, 15, 7, 14)])
+def test_non_square_grid_matches_oracle(P, Q, G, b, B):
+    n = 10000
+    I, J = plan_ref.factor_groups(P, Q, G)
+    for algo, L, W, _, _ in ALGOS:
+        c = hs.model_cost(algo, 2e-6, 1e-9, 0.0, n, P, Q, G, b, B)
+        inner, outer = cm.comm_grid(n, P, Q, I, J, b, B, L, W, 2e-6, 1e-9)
+        assert close(c["latency_inner"] + c["bandwidth_inner"], inner)
+        assert close(c["latency_outer"] + c["bandwidth_outer"], outer)
+
+
+def test_derivative_matches_eq10():
+    for n, p, b, al, be in ((8192, 128, 64, 1e-4, 1e-9), (65536, 16384, 256, 3e-6, 1e-9),
+                            (8192, 256, 64, 1e-7, 1e-9)):
+        for G in (1.0, 2.0, math.sqrt(p), p / 4, p):
+            assert close(hs.model_dcomm_dgroups(al, be, n, p, G, b),
+                         cm.dTHS_dG_vdg(n, p, G, b, al, be))
+
+
+@pytest.mark.parametrize("name", sorted(PLATFORMS))
+def test_selected_groups_are_the_oracle_brute_force(name):
+    pf = PLATFORMS[name]
+    n, P, Q, b, al, be = pf["n"], pf["P"], pf["Q"], pf["b"], pf["alpha"], pf["beta"]
+    counts = sorted({i * j for i in range(1, P + 1) if P % i == 0
+                     for j in range(1, Q + 1) if Q % j == 0})
+    for algo, L, W, _, _ in ALGOS:
+        for B in (b, 4 * b):
+            costs = []
+            for G in counts:
+                I, J = plan_ref.factor_groups(P, Q, G)
+                costs.append((sum(cm.comm_grid(n, P, Q, I, J, b, B, L, W, al, be)), G))
+            best_cost = min(c for c, _ in costs)
+            G, best, summa = hs.model_select_groups(algo, al, be, 0.0, n, P, Q, b, B)
+            assert close(best["comm"], best_cost)
+            assert G == min(g for c, g in costs if close(c, best_cost))
+            assert close(summa["comm"], sum(cm.comm_grid(n, P, Q, 1, 1, b, b, L, W, al, be)))
+    if P == Q and round(P ** 0.5) ** 2 == P:
+        # eq. (11) holds for all three platforms: with sqrt(p) = P arrangeable
+        # as sqrt(P) x sqrt(P) groups the optimum is G = sqrt(p)
+        G, _, _ = hs.model_select_groups(VDG, al, be, 0.0, n, P, Q, b, b)
+        assert G == P
+
+
+def test_below_the_threshold_summa_is_chosen():
+    # alpha/beta = 100 < 2 n b / p: sqrt(p) is the maximum (eq. (11)); G = 1
+    G, best, summa = hs.model_select_groups(VDG, 1e-7, 1e-9, 0.0, 8192, 16, 16, 64, 64)
+    assert G == 1 and close(best["comm"], summa["comm"])
+
+
+@pytest.mark.parametrize("call", [
+    lambda: hs.model_cost(VDG, 1e-6, 1e-9, 0.0, 1024, 4, 4, 3, 64, 64),       # G = 3 on 4 x 4
+    lambda: hs.model_cost(VDG, 1e-6, 1e-9, 0.0, 1024, 4, 4, 4, 128, 64),      # b > B
+    lambda: hs.model_cost(7, 1e-6, 1e-9, 0.0, 1024, 4, 4, 4, 64, 64),         # algorithm
+    lambda: hs.model_cost(VDG, -1.0, 1e-9, 0.0, 1024, 4, 4, 4, 64, 64),       # alpha < 0
+    lambda: hs.model_bcast(VDG, 1e-6, 1e-9, 10.0, 0.5),                       # q < 1
+    lambda: hs.model_dcomm_dgroups(1e-6, 1e-9, 1024, 16.0, 32.0, 64),         # G > p
+])
+def test_invalid_arguments(call):
+    with pytest.raises(hs.HsummaError) as ei:
+        call()
+    assert ei.value.code == hs.ERR_INVALID
