@@ -202,3 +202,97 @@ def build_dataset(shapes, reps: int = 3, log=None) -> list:
         if log and (i + 1) % 50 == 0:
             log("timed %d/%d shapes (%.0f s)" % (i + 1, len(shapes), time.time() - t0))
     return rows
+
+
+# -- the number of groups G: by the cost model and by sampling ---------------
+# The paper chooses G by sampling a few HSUMMA iterations with the valid
+# values (Sec. V-A2, Sec. VI); its model (Sec. IV) says whether G = sqrt(p)
+# beats SUMMA on a platform of latency alpha and reciprocal bandwidth beta.
+# On one GPU G changes no communication, only the order of the work items
+# (group by group, each group's tiles sharing an XCD's L2), so the sampled
+# times measure that effect alone.
+
+PLATFORMS = {   # the paper's parameter sets (Sec. V), seconds and seconds per element
+    "grid5000": dict(alpha=1e-4, beta=1e-9),
+    "bgp": dict(alpha=3e-6, beta=1e-9),
+    "exascale": dict(alpha=5e-7, beta=1e-11),
+}
+
+
+def group_counts(P: int, Q: int) -> list[int]:
+    return valid_groups(P, Q)
+
+
+def select_groups_by_model(n: int, P: int, Q: int, b: int, B: int, alpha: float, beta: float,
+                           algo: int = hs.BCAST_VAN_DE_GEIJN) -> dict:
+    G, best, summa = hs.model_select_groups(algo, alpha, beta, 0.0, n, P, Q, b, B)
+    return {"G": G, "comm_s": best["comm"], "summa_comm_s": summa["comm"],
+            "ratio": summa["comm"] / best["comm"] if best["comm"] > 0 else 1.0,
+            "sqrt_p_is_minimum": alpha / beta > 2.0 * n * b / (P * Q)}
+
+
+def select_groups_by_sampling(n: int, P: int, Q: int, b: int, M: int, counts=None,
+                              steps: int = 2, reps: int = 3, prec=hs.FP64) -> dict:
+    """Time `steps` outer steps of HSUMMA for every G (median of `reps`) and
+    keep the fastest: {"G": best, "ms": {G: ms per outer step}}."""
+    import torch
+    counts = counts or group_counts(P, Q)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4161)
+    A = torch.rand((n, n), dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+    B = torch.rand((n, n), dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+    C = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    plans = {G: hs.Plan(n, P, Q, G, b, M, prec=prec) for G in counts}
+    wss = {G: plans[G].workspace() for G in counts}
+    nsteps = min(steps, plans[counts[0]].num_outer_steps)
+
+    def run(G):
+        for s in range(nsteps):
+            plans[G].outer_update(s, A, B, C, ws=wss[G])
+    for G in counts:                        # warm-up: work items uploaded, clocks up
+        run(G)
+    torch.cuda.synchronize()
+    # the counts take turns in every repetition, so that clock or thermal
+    # drift during the sampling falls on all of them alike
+    times = {G: [] for G in counts}
+    for _ in range(reps):
+        for G in counts:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run(G)
+            e1.record(stream)
+            e1.synchronize()
+            times[G].append(e0.elapsed_time(e1) / nsteps)
+    for G in counts:
+        plans[G].close()
+    del A, B, C, wss
+    out = {G: sorted(v)[len(v) // 2] for G, v in times.items()}
+    return {"G": min(out, key=out.get), "ms": out}
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_1306_4161_amd.tune")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    gp = sub.add_parser("groups", help="choose G by the cost model and by sampling")
+    gp.add_argument("--n", type=int, default=8192)
+    gp.add_argument("--P", type=int, default=8)
+    gp.add_argument("--Q", type=int, default=8)
+    gp.add_argument("--b", type=int, default=64)
+    gp.add_argument("--M", type=int, default=256)
+    gp.add_argument("--steps", type=int, default=2)
+    gp.add_argument("--no-sample", action="store_true", help="model only (no GPU)")
+    args = ap.parse_args(argv)
+    res = {"shape": dict(n=args.n, P=args.P, Q=args.Q, b=args.b, M=args.M),
+           "model": {name: select_groups_by_model(args.n, args.P, args.Q, args.b, args.M, **pf)
+                     for name, pf in PLATFORMS.items()}}
+    if not args.no_sample:
+        res["sampled"] = select_groups_by_sampling(args.n, args.P, args.Q, args.b, args.M,
+                                                   steps=args.steps)
+    print(json.dumps(res, indent=1, sort_keys=True))
+
+
+if __name__ == "__main__":
+    main()

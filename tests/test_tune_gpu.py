@@ -38,3 +38,14 @@ def test_learned_model_beats_default_on_held_out_shapes():
     print(json.dumps({k: res[k] for k in ("regret_mlp", "regret_default", "best_static")}))
     assert res["regret_mlp"]["mean"] < res["regret_default"]["mean"]
     assert np.isfinite(res["regret_mlp"]["max"])
+
+
+def test_groups_by_sampling_and_by_model():
+    # the paper's procedure (Sec. V-A2): time a few HSUMMA iterations for
+    # every valid G and keep the fastest; every G computes the same product
+    res = tune.select_groups_by_sampling(1024, 4, 4, 32, 128, steps=2, reps=2)
+    assert set(res["ms"]) == set(tune.valid_groups(4, 4)) == {1, 2, 4, 8, 16}
+    assert res["G"] == min(res["ms"], key=res["ms"].get)
+    assert all(t > 0 for t in res["ms"].values())
+    m = tune.select_groups_by_model(1024, 4, 4, 32, 32, alpha=1e-4, beta=1e-9)
+    assert m["G"] == 4 and m["sqrt_p_is_minimum"]        # eq. (11): sqrt(16) = 4
