@@ -231,7 +231,7 @@ def main():
             per_launch = pairs * 2.0 * n * n * w
             peak = PEAK_BF16 if base == "bf16" else PEAK_FP8
             ach = per_launch / (pms * 1e-3) / 1e12
-            kern = "slice_bf16_kernel" if base == "bf16" else "slice_update_kernel<fp8>"
+            kern = "slice_bf16_kernel" if base == "bf16" else "slice_fp8_kernel"
             rec.update({"slices": sorted(set(sl)), "pairs": pairs,
                         "fp64_accurate": base == "bf16" and scaled <= GATE,
                         "dtype": "bf16" if base == "bf16" else "fp8-e4m3",

@@ -187,11 +187,12 @@ int hsumma_split_layout(hsumma_plan_t plan, size_t* off_digA, size_t* off_digB,
 
 /*
  * Self-test of the matrix-core accumulation the split forms rely on:
- * d (16 x 16 FP32, row-major) = a (16 x k digits, row-major) x b (k x 16
- * digits, row-major) by chained 16x16x32 MFMAs with FP32 accumulation,
- * fmt 0 = BF16 bit patterns (2 B), 1 = FP8-e4m3 bytes.  k a multiple of 32.
- * Integer digits whose partial sums stay within 2^24 must come back exact.
- * All pointers are device memory; asynchronous on `stream`.
+ * d (32 x 32 FP32, row-major) = a (32 x k digits, row-major) x b (k x 32
+ * digits, row-major) by chained 32x32x16 MFMAs (the slice kernels'
+ * instructions) with FP32 accumulation, fmt 0 = BF16 bit patterns (2 B),
+ * 1 = FP8-e4m3 bytes.  k a positive multiple of 16.  Integer digits whose
+ * partial sums stay within 2^24 must come back exact.  All pointers are
+ * device memory; asynchronous on `stream`.
  */
 int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k, float* d,
                             void* stream);

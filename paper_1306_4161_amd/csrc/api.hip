@@ -182,7 +182,7 @@ void build_items(hsumma_plan_s& p) {
   p.items_even = true;
   for (auto& it : p.items)
     if ((it.c0 | it.w) & 1) p.items_even = false;
-  if (p.opts.persistent || p.fmt == 0) {
+  if (p.opts.persistent || p.fmt >= 0) {
     // Longest-processing-time order inside each XCD's list, so that the
     // static round-robin of the persistent workgroups stays balanced when
     // tiles are uneven (ragged block-cyclic edges).
@@ -244,9 +244,9 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   if (rc) return rc;
   if (p->items.empty()) return HSUMMA_OK;
   int grid = 8 * p->per_xcd;
-  // the BF16 slice kernel always runs persistent (one workgroup per CU over
-  // its XCD's longest-first item list; measured as fast or faster)
-  const bool persistent = p->opts.persistent || p->fmt == 0;
+  // the slice kernels always run persistent (one workgroup per CU over its
+  // XCD's longest-first item list; measured as fast or faster for BF16)
+  const bool persistent = p->opts.persistent || p->fmt >= 0;
   if (persistent) {
     int dev = 0, cus = 0;
     HS_CHECK_HIP(hipGetDevice(&dev));
@@ -412,12 +412,12 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     p->cfg = cfg;
   } else {
     p->fmt = o.prec == HSUMMA_SPLIT_BF16 ? 0 : 1;
-    // BF16: 64 x 128 macro-tiles streamed in 16-k steps; FP8: 64 x 64, 32-k steps
-    const hs::TileCfg scfg = p->fmt == 0 ? hs::TileCfg{64, 128, 16} : hs::TileCfg{64, 64, 32};
+    // both forms: 64 x 128 macro-tiles streamed in 16-k steps
+    const hs::TileCfg scfg{64, 128, 16};
     if ((o.tile_m && o.tile_m != scfg.tm) || (o.tile_n && o.tile_n != scfg.tn) ||
         (o.kc && o.kc != scfg.kc)) {
       delete p;
-      return invalid("split forms use fixed macro-tiles (BF16 64 x 128 x 16, FP8 64 x 64 x 32)");
+      return invalid("split forms use fixed 64 x 128 macro-tiles and 16-k steps");
     }
     p->cfg = scfg;
     if (!p->opts.min_slices) p->opts.min_slices = 3;
@@ -669,7 +669,7 @@ int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k
                             void* stream) {
   if (fmt != 0 && fmt != 1) return invalid("fmt must be 0 (BF16) or 1 (FP8-e4m3)");
   if (!a || !b || !d) return invalid("null pointer");
-  if (k < 32 || k % 32) return invalid("k must be a positive multiple of 32");
+  if (k < 16 || k % 16) return invalid("k must be a positive multiple of 16");
   hipError_t e = hs::launch_mfma_probe(fmt, a, b, k, d, (hipStream_t)stream);
   if (e != hipSuccess) {
     set_error(std::string("probe launch: ") + hipGetErrorString(e));

@@ -20,7 +20,8 @@
 // accumulator.  BF16: levels 2..5 are exact accumulators (at most 4 pairs
 // x 64 k x 2^16 <= 2^24), deeper levels (weight <= 2^-36) share one
 // accumulator whose FP32 rounding stays below 2^-60 of the leading term;
-// every 64 k the accumulators are added into an FP64 panel sum.  FP8: every
+// each accumulator is added into an FP64 panel sum within its exactness
+// bound (every 64 or 128 k).  FP8: every
 // level is exact over the whole panel (7 pairs x 2^8 x w <= 2^24 for
 // w <= 9362) and is added, scaled by 2^(-T (L - 2)), at the end of the panel.
 // Finally C += 2^(e_i + f_j - 2H) x panel sum, in FP64.
@@ -352,236 +353,6 @@ __global__ void zero_u32_kernel(uint32_t* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// ---- slice products + recombination -----------------------------------------
-
-template <int FMT, int SMAX, int WM, int WN>
-struct SliceTile {
-  static constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
-  static constexpr int KC = 32;                          // k per MFMA step (one chunk)
-  static constexpr int ESZ = FMT == 0 ? 2 : 1;           // bytes per digit
-  static constexpr int ROWB = KC * ESZ + 16;             // LDS bytes per (plane, row)
-  static constexpr int UPR = KC * ESZ / 16;              // 16-byte units per (plane, row)
-  static constexpr int ABYTES = SMAX * TM * ROWB;
-  static constexpr int BBYTES = SMAX * TN * ROWB;
-  static constexpr int AUNITS = SMAX * TM * UPR;
-  static constexpr int BUNITS = SMAX * TN * UPR;
-  static constexpr int AU = (AUNITS + NT - 1) / NT;      // units per thread
-  static constexpr int BU = (BUNITS + NT - 1) / NT;
-  static constexpr int NACC = FMT == 0 ? (SMAX < 5 ? SMAX : 5) : SMAX;
-  static constexpr int REC = FMT == 0 ? 2 : 1 << 30;     // chunks between recombinations
-};
-
-template <int FMT, int SMAX, int WM, int WN>
-__global__ __launch_bounds__(WM * WN * 64, 1)
-void slice_update_kernel(SliceArgs p) {
-  using T = SliceTile<FMT, SMAX, WM, WN>;
-  constexpr int H = FMT == 0 ? 8 : 4;
-  constexpr int TB = FMT == 0 ? 9 : 5;
-  __shared__ __attribute__((aligned(16))) uint8_t smem[2 * (T::ABYTES + T::BBYTES)];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int l16 = lane & 15, lq = lane >> 4;
-
-  // slice count of this panel: fixed, or from the split's exponent statistics
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w, H, TB);
-  if (blockIdx.x == 0 && tid == 0 && p.slices_out) *p.slices_out = s;
-
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7;
-  const int slot0 = bid >> 3;
-  const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
-
-  for (int slot = slot0;; slot += slots) {
-    if (!p.persistent && slot != slot0) break;
-    if (slot >= p.per_xcd) break;
-    const int idx = xcd * p.per_xcd + slot;
-    if (idx >= p.nitems) break;
-    const WorkItem it = p.items[idx];
-
-    // global sources of this item's digit rows (rows past the item edge are
-    // clamped to its last row; their results are never stored)
-    const uint8_t* gA = (const uint8_t*)p.digA;
-    const uint8_t* gB = (const uint8_t*)p.digB;
-
-    uint4 sa[T::AU], sb[T::BU];
-    auto load_chunk = [&](int ch) {
-#pragma unroll
-      for (int q = 0; q < T::AU; ++q) {
-        const int u = tid + q * T::NT;
-        const int plane = u / (T::TM * T::UPR);
-        const int rr = (u / T::UPR) % T::TM;
-        const int part = u % T::UPR;
-        if (u < T::AUNITS && plane < s) {
-          const int row = it.r0 + min(rr, it.h - 1);
-          const int kb = (ch * T::KC * T::ESZ + part * 16) / (16 * T::ESZ);
-          const int ko = (ch * T::KC * T::ESZ + part * 16) % (16 * T::ESZ);
-          sa[q] = *(const uint4*)(gA + plane * p.planeA * T::ESZ +
-                                  (int64_t)kb * p.rowsA * 16 * T::ESZ + (int64_t)row * 16 * T::ESZ + ko);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < T::BU; ++q) {
-        const int u = tid + q * T::NT;
-        const int plane = u / (T::TN * T::UPR);
-        const int cc = (u / T::UPR) % T::TN;
-        const int part = u % T::UPR;
-        if (u < T::BUNITS && plane < s) {
-          const int col = it.c0 + min(cc, it.w - 1);
-          const int kb = (ch * T::KC * T::ESZ + part * 16) / (16 * T::ESZ);
-          const int ko = (ch * T::KC * T::ESZ + part * 16) % (16 * T::ESZ);
-          sb[q] = *(const uint4*)(gB + plane * p.planeB * T::ESZ +
-                                  (int64_t)kb * p.rowsB * 16 * T::ESZ + (int64_t)col * 16 * T::ESZ + ko);
-        }
-      }
-    };
-    auto store_chunk = [&](uint8_t* base) {
-      uint8_t* As = base;
-      uint8_t* Bs = base + T::ABYTES;
-#pragma unroll
-      for (int q = 0; q < T::AU; ++q) {
-        const int u = tid + q * T::NT;
-        const int plane = u / (T::TM * T::UPR);
-        const int rr = (u / T::UPR) % T::TM;
-        const int part = u % T::UPR;
-        if (u < T::AUNITS && plane < s)
-          *(uint4*)(As + (plane * T::TM + rr) * T::ROWB + part * 16) = sa[q];
-      }
-#pragma unroll
-      for (int q = 0; q < T::BU; ++q) {
-        const int u = tid + q * T::NT;
-        const int plane = u / (T::TN * T::UPR);
-        const int cc = (u / T::UPR) % T::TN;
-        const int part = u % T::UPR;
-        if (u < T::BUNITS && plane < s)
-          *(uint4*)(Bs + (plane * T::TN + cc) * T::ROWB + part * 16) = sb[q];
-      }
-    };
-
-    f4 acc[T::NACC][2][2];
-    double cp[2][2][4];
-#pragma unroll
-    for (int a = 0; a < T::NACC; ++a)
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[a][x][y] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cp[x][y][v] = 0.0;
-
-    auto recombine = [&]() {
-#pragma unroll
-      for (int a = T::NACC - 1; a >= 0; --a) {   // smallest weight first
-        const double wgt = FMT == 0 ? 1.0 : ldexp(1.0, -TB * a);
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) cp[x][y][v] = fma((double)acc[a][x][y][v], wgt, cp[x][y][v]);
-            acc[a][x][y] = f4{0.f, 0.f, 0.f, 0.f};
-          }
-      }
-    };
-
-    const int nch = p.nchunks;
-    load_chunk(0);
-    store_chunk(smem);
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-      const int buf = ch & 1;
-      if (ch + 1 < nch) load_chunk(ch + 1);
-      const uint8_t* As = smem + buf * (T::ABYTES + T::BBYTES);
-      const uint8_t* Bs = As + T::ABYTES;
-      if (FMT == 0) {
-        bf8v bfr[SMAX][2];
-#pragma unroll
-        for (int l2 = 0; l2 < SMAX; ++l2)
-          if (l2 < s)
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-              bfr[l2][y] = *(const bf8v*)(Bs + (l2 * T::TN + wn * 32 + y * 16 + l16) * T::ROWB + lq * 16);
-#pragma unroll
-        for (int l1 = 0; l1 < SMAX; ++l1) {
-          if (l1 < s) {
-            bf8v afr[2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-              afr[x] = *(const bf8v*)(As + (l1 * T::TM + wm * 32 + x * 16 + l16) * T::ROWB + lq * 16);
-#pragma unroll
-            for (int l2 = 0; l2 < SMAX; ++l2) {
-              if (l1 + l2 < s) {
-                constexpr int dummy = 0;
-                (void)dummy;
-                const int a = (l1 + l2) < T::NACC - 1 ? (l1 + l2) : T::NACC - 1;
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                  for (int y = 0; y < 2; ++y)
-                    acc[a][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[x], bfr[l2][y], acc[a][x][y], 0, 0, 0);
-              }
-            }
-          }
-        }
-      } else {
-        long bfr[SMAX][2];
-#pragma unroll
-        for (int l2 = 0; l2 < SMAX; ++l2)
-          if (l2 < s)
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-              bfr[l2][y] = *(const long*)(Bs + (l2 * T::TN + wn * 32 + y * 16 + l16) * T::ROWB + lq * 8);
-#pragma unroll
-        for (int l1 = 0; l1 < SMAX; ++l1) {
-          if (l1 < s) {
-            long afr[2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-              afr[x] = *(const long*)(As + (l1 * T::TM + wm * 32 + x * 16 + l16) * T::ROWB + lq * 8);
-#pragma unroll
-            for (int l2 = 0; l2 < SMAX; ++l2) {
-              if (l1 + l2 < s) {
-                const int a = l1 + l2;
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                  for (int y = 0; y < 2; ++y)
-                    acc[a][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(afr[x], bfr[l2][y], acc[a][x][y], 0, 0, 0);
-              }
-            }
-          }
-        }
-      }
-      if ((ch + 1) % T::REC == 0 || ch + 1 == nch) recombine();
-      if (ch + 1 < nch) store_chunk(smem + (buf ^ 1) * (T::ABYTES + T::BBYTES));
-      __syncthreads();
-    }
-
-    // C += 2^(e_i + f_j - 2H) x panel sum
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const int col = wn * 32 + y * 16 + l16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = wm * 32 + x * 16 + 4 * lq + v;
-          if (row < it.h && col < it.w) {
-            const int gr = it.r0 + row, gc = it.c0 + col;
-            const double add = ldexp(cp[x][y][v], p.eA[gr] + p.fB[gc] - 2 * H);
-            double* cptr = p.C + (int64_t)gr * p.ldc + gc;
-            *cptr = p.zero_init ? add : *cptr + add;
-          }
-        }
-      }
-    }
-  }
-}
-
 // ---- BF16 slice products, streamed ------------------------------------------
 // Workgroup tile 64 x 128, 4 waves (2 x 2, one per SIMD) of a 32 x 64 block
 // each (two 32x32 blocks sharing the A fragment), on
@@ -891,39 +662,250 @@ __global__ __launch_bounds__(256, 1) void slice_bf16_kernel(SliceArgs p) {
   }
 }
 
+// ---- FP8 slice products, streamed -------------------------------------------
+// The BF16 kernel's design with e4m3 digits on v_mfma_f32_32x32x16_fp8_fp8
+// (lane l holds A[l % 32][8 (l / 32) .. + 7] and B[8 (l / 32) .. + 7][l % 32],
+// 8 bytes each; D as for the BF16 instruction).  Per 16-k step a plane is 64
+// rows x 16 bytes of A (one wave-instruction of 64 16-byte units) and
+// 128 x 16 bytes of B (two), so a step is 3 S wave-instructions, dealt
+// round-robin over the 4 waves.  A plane's LDS image is its HBM layout
+// ([row][16 bytes]); a fragment read (32 rows x 16 bytes) is 512 contiguous
+// bytes, free of bank conflicts.  Every level of e4m3 digit pairs stays
+// exact in FP32 over a whole panel (at most 7 pairs of |d d'| <= 2^8 per k,
+// panels of at most 8192 k), so each level keeps its own accumulator from
+// the item's first step to its last and is added into FP64 once, scaled by
+// 2^(-5 a), smallest weight first.
+constexpr int kFp8Lds = 152 * 1024;   // LDS ring budget (bytes)
+constexpr int fp8_stages(int S) {
+  return kFp8Lds / (S * 192 * 16) < 5 ? kFp8Lds / (S * 192 * 16) : 5;
+}
+
+template <int S>
+__device__ __forceinline__ void slice_fp8_items(const SliceArgs& p, uint8_t* smem) {
+  constexpr int TM = 64, TN = 128, NS = fp8_stages(S);
+  constexpr int ABYTES = S * TM * 16, BBYTES = S * TN * 16, SB = ABYTES + BBYTES;
+  constexpr int NI = 3 * S;                           // wave-instructions per step
+  constexpr int NILO = NI / 4, NIHI = NILO + (NI % 4 ? 1 : 0);
+  constexpr int LAG = S < 3 ? S : (S <= 5 ? 2 : 3);   // rows of reads ahead of the MFMAs
+  constexpr int H = 4, T = 5;
+  static_assert(NS >= 3 && NS * SB <= kFp8Lds, "LDS ring");
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const bool hi = wave < NI % 4;                // this wave issues NIHI per step
+
+  const __amdgpu_buffer_rsrc_t rsrcA =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.digA, (short)0, (int)p.bytesA, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rsrcB =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.digB, (short)0, (int)p.bytesB, kBufferWord3);
+  const uint32_t kbA = (uint32_t)p.rowsA * 16u, kbB = (uint32_t)p.rowsB * 16u;  // per k16 block
+  const uint32_t planeAB = (uint32_t)p.planeA, planeBB = (uint32_t)p.planeB;   // 1-byte digits
+  const int nsteps = p.Wp / 16;                // even: the panel is padded to 32 k
+  const int aoff = (wm * 32 + l32) * 16 + lh * 8;
+  const int boff = (wn * 64 + l32) * 16 + lh * 8;   // block 1: 32 columns (512 bytes) on
+
+  const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
+  const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
+
+  for (int slot = slot0;; slot += slots) {
+    if (!p.persistent && slot != slot0) break;
+    if (slot >= p.per_xcd) break;
+    const int idx = xcd * p.per_xcd + slot;
+    if (idx >= p.nitems) break;
+    const WorkItem it = p.items[idx];
+
+    // per-lane byte offsets of the lane's row of A and columns of B (ragged
+    // edges clamped to the last valid one); plane and k16 block are uniform
+    const uint32_t voffA = (uint32_t)(it.r0 + min(lane, it.h - 1)) * 16u;
+    const uint32_t voffB0 = (uint32_t)(it.c0 + min(lane, it.w - 1)) * 16u;
+    const uint32_t voffB1 = (uint32_t)(it.c0 + min(64 + lane, it.w - 1)) * 16u;
+    auto dma = [&](__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint8_t* dst) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          r, (__attribute__((address_space(3))) void*)dst, 16, voff, soff, 0, 0);
+    };
+    // instruction i of a step: plane i / 3; A (i % 3 == 0) or B columns
+    // 0..63 / 64..127; issued by wave i % 4, so a wave walks i = wave,
+    // wave + 4, ... (a uniform loop: unrolled over every instruction and
+    // stage, the scalar offsets alone spill the scalar file)
+    auto issue = [&](int kb, int st) {
+      uint8_t* stage = smem + st * SB;
+      const int cnt = hi ? NIHI : NILO;
+#pragma unroll 1
+      for (int j = 0; j < cnt; ++j) {
+        const int i = wave + 4 * j;
+        const int l = i / 3, kind = i - 3 * l;
+        if (kind == 0)
+          dma(rsrcA, voffA, (uint32_t)(l * planeAB + kb * kbA), stage + l * (TM * 16));
+        else
+          dma(rsrcB, kind == 1 ? voffB0 : voffB1, (uint32_t)(l * planeBB + kb * kbB),
+              stage + ABYTES + l * (TN * 16) + (kind - 1) * 1024);
+      }
+    };
+    auto wait_step = [&](int later) {
+      if (hi) vm_wait_steps<NIHI, NS - 1>(later);
+      else vm_wait_steps<NILO, NS - 1>(later);
+    };
+
+    f16v acc0[S], acc1[S];                     // one accumulator per level, blocks 0 and 1
+    // fragments: row r pairs A plane S-1-r with B planes 0 .. r; reads run LAG
+    // rows ahead, the last LAG rows of a step reading the next step's first
+    // rows into the other register set
+    long fa[2][S], fb0[2][S], fb1[2][S];
+    auto read_row = [&](int set, int st, int r) {
+      const uint8_t* sA = smem + st * SB;
+      const uint8_t* sB = sA + ABYTES;
+      fa[set][S - 1 - r] = *(const long*)(sA + (S - 1 - r) * (TM * 16) + aoff);
+      fb0[set][r] = *(const long*)(sB + r * (TN * 16) + boff);
+      fb1[set][r] = *(const long*)(sB + r * (TN * 16) + boff + 512);
+    };
+    // in the item's first step each level's first pair (row S-1-a, l2 = 0)
+    // takes a zero C operand
+    const f16v zero = {};
+    auto row = [&](int set, int r, bool first) {
+      const int l1 = S - 1 - r;
+#pragma unroll
+      for (int l2 = 0; l2 <= r; ++l2) {
+        const int a = l1 + l2;
+        const bool z = first && l2 == 0;
+        acc0[a] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(fa[set][l1], fb0[set][l2],
+                                                             z ? zero : acc0[a], 0, 0, 0);
+        acc1[a] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(fa[set][l1], fb1[set][l2],
+                                                             z ? zero : acc1[a], 0, 0, 0);
+      }
+    };
+    auto step = [&](int ci, int cur, bool first) {
+      const int nxt = cur ^ 1;
+      const bool more = ci + 1 < nsteps;
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        if (r == S - LAG && more) {
+          wait_step(min(NS - 2, nsteps - 2 - ci));   // step ci + 1 landed (this wave)
+          ring_barrier();
+          if (ci + NS < nsteps) issue(ci + NS, ci % NS);
+        }
+        if (r + LAG < S) read_row(cur, ci % NS, r + LAG);
+        else if (more) read_row(nxt, (ci + 1) % NS, r + LAG - S);
+        row(cur, r, first);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+      if (st < nsteps) issue(st, st);
+    wait_step(min(NS - 1, nsteps - 1));
+    ring_barrier();
+#pragma unroll
+    for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
+    step(0, 0, true);
+    int ci = 1;
+    for (; ci + 2 <= nsteps; ci += 2) {
+      step(ci, 1, false);
+      step(ci + 1, 0, false);
+    }
+    if (ci < nsteps) step(ci, 1, false);
+    __syncthreads();  // the ring is reused by the next item
+
+    double cp0[16], cp1[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      cp0[v] = 0.0;
+      cp1[v] = 0.0;
+    }
+#pragma unroll
+    for (int a = S - 1; a >= 0; --a) {
+      const double wgt = ldexp(1.0, -T * a);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        cp0[v] = fma((double)acc0[a][v], wgt, cp0[v]);
+        cp1[v] = fma((double)acc1[a][v], wgt, cp1[v]);
+      }
+    }
+
+    // C += 2^(e_i + f_j - 2H) x panel sum (clamped loads, predicated stores).
+    // The lane's rows and columns are derived afresh from an opaque lane id:
+    // hoisted out of the item loop they stay live across it and spill.
+    int lane_e;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane_e));
+    const int l32e = lane_e & 31, lhe = lane_e >> 5;
+    auto erow_e = [&](int v) { return wm * 32 + 8 * (v >> 2) + 4 * lhe + (v & 3); };
+    int ea[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) ea[v] = p.eA[it.r0 + min(erow_e(v), it.h - 1)];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int col = wn * 64 + q * 32 + l32e;
+      const int fq = p.fB[it.c0 + min(col, it.w - 1)];
+      double cold[16];
+      if (!p.zero_init) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          cold[v] = p.C[(int64_t)(it.r0 + min(erow_e(v), it.h - 1)) * p.ldc + it.c0 +
+                        min(col, it.w - 1)];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = erow_e(v);
+        const double add = ldexp(q ? cp1[v] : cp0[v], ea[v] + fq - 2 * H);
+        if (row < it.h && col < it.w)
+          p.C[(int64_t)(it.r0 + row) * p.ldc + it.c0 + col] = p.zero_init ? add : cold[v] + add;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void slice_fp8_kernel(SliceArgs p) {
+  __shared__ __attribute__((aligned(1024))) uint8_t smem[kFp8Lds];
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w, 4, 5);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
+  switch (s) {
+    case 1: slice_fp8_items<1>(p, smem); break;
+    case 2: slice_fp8_items<2>(p, smem); break;
+    case 3: slice_fp8_items<3>(p, smem); break;
+    case 4: slice_fp8_items<4>(p, smem); break;
+    case 5: slice_fp8_items<5>(p, smem); break;
+    case 6: slice_fp8_items<6>(p, smem); break;
+    default: slice_fp8_items<7>(p, smem); break;
+  }
+}
+
 // ---- self-test of the matrix-core accumulation -------------------------------
-// D (16 x 16, FP32) = A (16 x k digits, row-major) x B (k x 16 digits,
-// row-major) by chained 16x16x32 MFMAs with FP32 accumulation, exactly as the
-// slice-product kernel accumulates one level.  One wave.
+// D (32 x 32, FP32) = A (32 x k digits, row-major) x B (k x 32 digits,
+// row-major) by chained 32x32x16 MFMAs with FP32 accumulation -- the
+// instructions and operand layout of the slice-product kernels (lane l holds
+// A[l % 32][8 (l / 32) .. + 7] and B[8 (l / 32) .. + 7][l % 32]; D item v
+// of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]).  One wave.
 template <int FMT>
 __global__ __launch_bounds__(64) void mfma_probe_kernel(const void* a, const void* b, int k,
                                                          float* out) {
-  const int l = threadIdx.x, l16 = l & 15, lq = l >> 4;
-  f4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int kc = 0; kc < k; kc += 32) {
+  const int l = threadIdx.x, l32 = l & 31, lh = l >> 5;
+  f16v acc = {};
+  for (int kc = 0; kc < k; kc += 16) {
     if (FMT == 0) {
       const uint16_t* A = (const uint16_t*)a;
       const uint16_t* B = (const uint16_t*)b;
       bf8v av, bv;
       for (int e = 0; e < 8; ++e) {
-        const int kk = kc + lq * 8 + e;
-        av[e] = __builtin_bit_cast(__bf16, A[l16 * k + kk]);
-        bv[e] = __builtin_bit_cast(__bf16, B[kk * 16 + l16]);
+        const int kk = kc + 8 * lh + e;
+        av[e] = __builtin_bit_cast(__bf16, A[l32 * k + kk]);
+        bv[e] = __builtin_bit_cast(__bf16, B[kk * 32 + l32]);
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     } else {
       const uint8_t* A = (const uint8_t*)a;
       const uint8_t* B = (const uint8_t*)b;
       long av = 0, bv = 0;
       for (int e = 0; e < 8; ++e) {
-        const int kk = kc + lq * 8 + e;
-        av |= (long)A[l16 * k + kk] << (8 * e);
-        bv |= (long)B[kk * 16 + l16] << (8 * e);
+        const int kk = kc + 8 * lh + e;
+        av |= (long)A[l32 * k + kk] << (8 * e);
+        bv |= (long)B[kk * 32 + l32] << (8 * e);
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(av, bv, acc, 0, 0, 0);
     }
   }
-  for (int v = 0; v < 4; ++v) out[(4 * lq + v) * 16 + l16] = acc[v];
+  for (int v = 0; v < 16; ++v) out[(8 * (v >> 2) + 4 * lh + (v & 3)) * 32 + l32] = acc[v];
 }
 
 hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float* out,
@@ -956,7 +938,7 @@ hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s) {
   if (fmt == 0)
     hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((slice_update_kernel<1, kSplitMaxSlices, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(slice_fp8_kernel, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -286,10 +286,12 @@ class Plan:
 
 
 def mfma_exact_probe(fmt, a_digits, b_digits, stream=None):
-    """16 x 16 FP32 product of digit matrices on the matrix cores (see header)."""
+    """32 x 32 FP32 product of digit matrices on the matrix cores (see header)."""
     import torch
     k = a_digits.shape[1]
-    d = torch.empty((16, 16), dtype=torch.float32, device="cuda")
+    if a_digits.shape[0] != 32 or b_digits.shape != (k, 32):
+        raise ValueError("the probe takes a 32 x k and a k x 32 digit matrix")
+    d = torch.empty((32, 32), dtype=torch.float32, device="cuda")
     _check(lib().hsumma_mfma_exact_probe(fmt, ctypes.c_void_p(a_digits.data_ptr()),
                                          ctypes.c_void_p(b_digits.data_ptr()), k,
                                          ctypes.c_void_p(d.data_ptr()), _stream(stream)))
