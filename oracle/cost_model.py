@@ -41,6 +41,8 @@ Functions
   optimal_vdg(n, p, b, alpha, beta)          eq. (12)
   comm_grid(n, P, Q, I, J, b, B, L, W, alpha, beta)   the non-square reading
   exascale_plot(n, p, G, b, alpha, beta, gamma)   the curves of Fig. 10
+  comm_levels(n, P, Q, Is, Js, blocks, L, W, alpha, beta)   more than two levels
+  levels_vdg(n, p, levels, b, alpha, beta)   their equal-fan-out closed form
 """
 from __future__ import annotations
 
@@ -160,3 +162,30 @@ def exascale_plot(n, p, G, b, alpha, beta, gamma):
     su = comp + (n / b) * (log2(p) + 2 * (math.sqrt(p) - 1)) * alpha \
         + 4 * (n * n / math.sqrt(p)) * (1 - 1 / math.sqrt(p)) * beta
     return hs, su
+
+
+# -- more than two levels (the paper's future work, Sec. VI) -----------------
+# Level 0 is the outermost.  Level l arranges its units I_l x J_l (the
+# products over the levels are P and Q) and moves blocks of width B_l
+# (non-increasing, the innermost being b): every B_l-step broadcasts A's
+# n B_l / P elements per process along J_l units of a row and B's n B_l / Q
+# along I_l units of a column.  Two levels (I, J), (P/I, Q/J) with (B, b)
+# are HSUMMA; one level (P, Q) with b is SUMMA.
+
+def comm_levels(n, P, Q, Is, Js, blocks, L, W, alpha, beta):
+    """Seconds of every level's broadcasts, outermost first."""
+    out = []
+    for I, J, Bl in zip(Is, Js, blocks):
+        row = L(J) * alpha + n * Bl / P * W(J) * beta
+        col = L(I) * alpha + n * Bl / Q * W(I) * beta
+        out.append(n / Bl * (row + col))
+    return out
+
+
+def levels_vdg(n, p, levels, b, alpha, beta):
+    """Van de Geijn cost with `levels` levels of equal fan-out p^(1/(2 levels))
+    per dimension on a sqrt(p) x sqrt(p) grid, b at every level; levels = 1
+    is SUMMA (Table II), levels = 2 the optimum of eq. (12)."""
+    q = p ** (1.0 / (2 * levels))
+    return ((log2(p) + 2 * levels * (q - 1)) * n / b * alpha
+            + 4 * levels * (1 - 1 / q) * n * n / math.sqrt(p) * beta)

@@ -163,3 +163,31 @@ def test_grid_form_is_symmetric_under_transposition(P, Q, I, J):
         # one group: nothing between groups; one process per group: nothing inside
         assert cm.comm_grid(n, P, Q, 1, 1, b, B, L, W, 2e-6, 1e-9)[1] == 0.0
         assert cm.comm_grid(n, P, Q, P, Q, b, B, L, W, 2e-6, 1e-9)[0] == 0.0
+
+
+def test_levels_reduce_to_summa_and_hsumma():
+    n, P, Q, b, B = 8192, 16, 8, 64, 256
+    for L, W in ((cm.L_vdg, cm.W_vdg), (cm.L_binomial, cm.W_binomial)):
+        one = cm.comm_levels(n, P, Q, [P], [Q], [b], L, W, 2e-6, 1e-9)
+        assert close(sum(one), sum(cm.comm_grid(n, P, Q, 1, 1, b, b, L, W, 2e-6, 1e-9)))
+        two = cm.comm_levels(n, P, Q, [4, P // 4], [2, Q // 2], [B, b], L, W, 2e-6, 1e-9)
+        inner, outer = cm.comm_grid(n, P, Q, 4, 2, b, B, L, W, 2e-6, 1e-9)
+        assert close(two[0], outer) and close(two[1], inner)
+        # a level of one unit moves nothing
+        three = cm.comm_levels(n, P, Q, [1, 4, P // 4], [1, 2, Q // 2], [1024, B, b], L, W,
+                               2e-6, 1e-9)
+        assert three[0] == 0.0 and close(three[1], outer) and close(three[2], inner)
+
+
+@pytest.mark.parametrize("name", sorted(PLATFORMS))
+def test_levels_closed_form(name):
+    pf = PLATFORMS[name]
+    n, p, b, al, be = pf["n"], pf["p"], pf["b"], pf["alpha"], pf["beta"]
+    assert close(cm.levels_vdg(n, p, 1, b, al, be), sum(cm.summa_vdg(n, p, b, al, be)))
+    assert close(cm.levels_vdg(n, p, 2, b, al, be), cm.optimal_vdg(n, p, b, al, be), rel=1e-11)
+    # equal fan-out at every level on a grid where it is an integer
+    for levels, q in ((3, 4), (2, 8), (4, 2)):
+        P = q ** levels
+        per = cm.comm_levels(n, P, P, [q] * levels, [q] * levels, [b] * levels,
+                             cm.L_vdg, cm.W_vdg, al, be)
+        assert close(sum(per), cm.levels_vdg(n, P * P, levels, b, al, be), rel=1e-11)
