@@ -246,6 +246,19 @@ int hsumma_model_cost(int32_t algo, const hsumma_platform* pf, int64_t n, int32_
  * (1, p) iff alpha / beta > 2 n b / p (eq. (11)). */
 int hsumma_model_dcomm_dgroups(const hsumma_platform* pf, int64_t n, double p, double G,
                                int64_t b, double* derivative);
+/* More than two levels of groups (the paper's future work, Sec. VI): level
+ * l (0 = outermost, nlevels <= 16) arranges its units I[l] x J[l] (the
+ * products over the levels must be P and Q) and moves blocks of width
+ * blocks[l] (non-increasing): every such step broadcasts A's n blocks[l] / P
+ * elements per process along J[l] units of a row and B's n blocks[l] / Q
+ * along I[l] units of a column.  One level (P, Q) with b is SUMMA; two
+ * levels (I, J), (P/I, Q/J) with (B, b) give hsumma_model_cost.  In `out`
+ * the innermost level fills the *_inner terms and all other levels the
+ * *_outer terms; per_level (nullable, nlevels entries) receives each
+ * level's seconds. */
+int hsumma_model_cost_levels(int32_t algo, const hsumma_platform* pf, int64_t n, int32_t P,
+                             int32_t Q, int32_t nlevels, const int32_t* I, const int32_t* J,
+                             const int64_t* blocks, hsumma_cost* out, double* per_level);
 /* The G with the least modelled communication time over every group count
  * that the P x Q grid can arrange (costs within a relative 1e-12 of the
  * least go to the smaller G), its cost, and the cost of SUMMA (G = 1).  Any

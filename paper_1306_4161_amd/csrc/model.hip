@@ -119,6 +119,49 @@ int hsumma_model_dcomm_dgroups(const hsumma_platform* pf, int64_t n, double p, d
   return HSUMMA_OK;
 }
 
+int hsumma_model_cost_levels(int32_t algo, const hsumma_platform* pf, int64_t n, int32_t P,
+                             int32_t Q, int32_t nlevels, const int32_t* I, const int32_t* J,
+                             const int64_t* blocks, hsumma_cost* out, double* per_level) {
+  if (!out || !I || !J || !blocks || !platform_ok(pf)) return model_invalid("null or invalid argument");
+  if (!algo_ok(algo)) return model_invalid("unknown broadcast algorithm");
+  if (n < 1 || P < 1 || Q < 1) return model_invalid("sizes must be positive");
+  if (nlevels < 1 || nlevels > 16) return model_invalid("need 1 <= nlevels <= 16");
+  int64_t pi = 1, pj = 1;
+  for (int l = 0; l < nlevels; ++l) {
+    if (I[l] < 1 || J[l] < 1 || blocks[l] < 1) return model_invalid("level sizes must be positive");
+    if (l > 0 && blocks[l] > blocks[l - 1])
+      return model_invalid("blocks must not grow from the outer to the inner levels");
+    pi *= I[l];
+    pj *= J[l];
+    if (pi > P || pj > Q) break;
+  }
+  if (pi != P || pj != Q) return model_invalid("the levels' arrangements must multiply to P x Q");
+  *out = hsumma_cost{};
+  const double nd = (double)n;
+  for (int l = 0; l < nlevels; ++l) {
+    const double steps = nd / (double)blocks[l];
+    double L, W, lat = 0.0, band = 0.0;
+    factors(algo, (double)J[l], &L, &W);      // A's block along a row
+    lat += steps * L * pf->alpha;
+    band += steps * (nd * blocks[l] / P) * W * pf->beta;
+    factors(algo, (double)I[l], &L, &W);      // B's block along a column
+    lat += steps * L * pf->alpha;
+    band += steps * (nd * blocks[l] / Q) * W * pf->beta;
+    if (l == nlevels - 1) {
+      out->latency_inner = lat;
+      out->bandwidth_inner = band;
+    } else {
+      out->latency_outer += lat;
+      out->bandwidth_outer += band;
+    }
+    if (per_level) per_level[l] = lat + band;
+  }
+  out->comm = out->latency_inner + out->latency_outer + out->bandwidth_inner + out->bandwidth_outer;
+  out->comp = 2.0 * nd * nd * nd / ((double)P * Q) * pf->gamma;
+  out->total = out->comp + out->comm;
+  return HSUMMA_OK;
+}
+
 int hsumma_model_select_groups(int32_t algo, const hsumma_platform* pf, int64_t n, int32_t P,
                                int32_t Q, int64_t b, int64_t B, int32_t* G_best,
                                hsumma_cost* best, hsumma_cost* summa) {

@@ -24,7 +24,7 @@ EXPORTED = [
     "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
     "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
     "hsumma_mlp_adam", "hsumma_model_bcast", "hsumma_model_cost", "hsumma_model_dcomm_dgroups",
-    "hsumma_model_select_groups",
+    "hsumma_model_select_groups", "hsumma_model_cost_levels",
 ]
 
 BCAST_BINOMIAL, BCAST_VAN_DE_GEIJN = 0, 1
@@ -113,6 +113,8 @@ def lib():
         L.hsumma_model_dcomm_dgroups.argtypes = [P(Platform), i64, dbl, dbl, i64, P(dbl)]
         L.hsumma_model_select_groups.argtypes = [i32, P(Platform), i64, i32, i32, i64, i64, P(i32),
                                                  P(Cost), P(Cost)]
+        L.hsumma_model_cost_levels.argtypes = [i32, P(Platform), i64, i32, i32, i32, P(i32), P(i32),
+                                               P(i64), P(Cost), P(dbl)]
         L.hsumma_last_error.restype = ctypes.c_char_p
         L.hsumma_last_error.argtypes = []
         L.hsumma_version.restype = ctypes.c_char_p
@@ -392,3 +394,19 @@ def model_select_groups(algo, alpha, beta, gamma, n, P, Q, b, B):
     _check(lib().hsumma_model_select_groups(algo, ctypes.byref(pf), n, P, Q, b, B, ctypes.byref(g),
                                             ctypes.byref(best), ctypes.byref(summa)))
     return g.value, best.as_dict(), summa.as_dict()
+
+
+def model_cost_levels(algo, alpha, beta, gamma, n, P, Q, Is, Js, blocks):
+    """(cost, per-level seconds) of a hierarchy of len(Is) levels, outermost first."""
+    k = len(Is)
+    if len(Js) != k or len(blocks) != k:
+        raise ValueError("one I, J and block per level")
+    ia = (ctypes.c_int32 * k)(*Is)
+    ja = (ctypes.c_int32 * k)(*Js)
+    ba = (ctypes.c_int64 * k)(*blocks)
+    per = (ctypes.c_double * k)()
+    c = Cost()
+    pf = Platform(alpha, beta, gamma)
+    _check(lib().hsumma_model_cost_levels(algo, ctypes.byref(pf), n, P, Q, k, ia, ja, ba,
+                                          ctypes.byref(c), per))
+    return c.as_dict(), list(per)

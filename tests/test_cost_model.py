@@ -136,3 +136,35 @@ def test_invalid_arguments(call):
     with pytest.raises(hs.HsummaError) as ei:
         call()
     assert ei.value.code == hs.ERR_INVALID
+
+
+@pytest.mark.parametrize("P,Q,Is,Js,blocks", [
+    (16, 8, [16], [8], [64]),
+    (16, 8, [4, 4], [2, 4], [256, 64]),
+    (64, 64, [4, 4, 4], [4, 4, 4], [256, 256, 256]),
+    (24, 30, [2, 3, 4], [5, 3, 2], [512, 128, 32]),
+    (8, 8, [1, 2, 4], [1, 4, 2], [1024, 256, 64]),
+])
+def test_levels_match_oracle(P, Q, Is, Js, blocks):
+    n = 12000
+    for algo, L, W, _, _ in ALGOS:
+        c, per = hs.model_cost_levels(algo, 2e-6, 1e-9, 1e-12, n, P, Q, Is, Js, blocks)
+        ref = cm.comm_levels(n, P, Q, Is, Js, blocks, L, W, 2e-6, 1e-9)
+        assert all(close(a, r) for a, r in zip(per, ref))
+        assert close(c["latency_inner"] + c["bandwidth_inner"], ref[-1])
+        assert close(c["comm"], sum(ref)) and close(c["comp"], 2 * n ** 3 / (P * Q) * 1e-12)
+    if len(Is) == 2:   # two levels are hsumma_model_cost in the plan's arrangement of G
+        G = Is[0] * Js[0]
+        I, J = plan_ref.factor_groups(P, Q, G)
+        a = hs.model_cost(VDG, 2e-6, 1e-9, 0.0, n, P, Q, G, blocks[1], blocks[0])
+        b, _ = hs.model_cost_levels(VDG, 2e-6, 1e-9, 0.0, n, P, Q, [I, P // I], [J, Q // J],
+                                    blocks)
+        assert close(a["comm"], b["comm"])
+
+
+def test_levels_reject_bad_hierarchies():
+    for Is, Js, blocks in (([2, 2], [2, 2], [64, 64]),      # 4 x 4 is not 8 x 8
+                           ([2, 4], [4, 2], [64, 256]),     # blocks grow inwards
+                           ([8], [8], [0])):
+        with pytest.raises(hs.HsummaError):
+            hs.model_cost_levels(VDG, 1e-6, 1e-9, 0.0, 1024, 8, 8, Is, Js, blocks)
