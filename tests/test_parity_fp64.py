@@ -202,3 +202,38 @@ def test_c3_block_cyclic_persistent_graph():
     # the direct (non-graph, non-persistent) launch gives the same bits
     q = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC)
     assert np.array_equal(_run(q, dA, dB), Cn)
+
+
+@pytest.mark.parametrize("prec", [hs.FP64, hs.SPLIT_BF16])
+def test_checkpoint_resume_bitwise(prec):
+    # the step boundary is a checkpoint: C after outer step s is the product
+    # over the first s panels; a new plan can resume from it
+    import torch
+    _say("case checkpoint/resume prec=%d" % prec)
+    n, P, Q, G, b, M = 768, 3, 4, 6, 32, 128
+    A = dev(inputs.uniform(n, n, 71))
+    B = dev(inputs.uniform(n, n, 72))
+    p = hs.Plan(n, P, Q, G, b, M, prec=prec)
+    ws = p.workspace()
+    ref = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    p.run(A, B, ref, ws=ws)
+    again = torch.empty_like(ref)
+    p.run(A, B, again, ws=ws)
+    assert torch.equal(ref, again)                       # run-to-run determinism
+    nout = p.num_outer_steps
+    p.close()
+    C = torch.zeros_like(ref)
+    first = hs.Plan(n, P, Q, G, b, M, prec=prec)
+    ws1 = first.workspace()
+    for g in range(nout // 2):
+        first.outer_update(g, A, B, C, ws=ws1)
+    torch.cuda.synchronize()
+    first.close()
+    del ws1
+    second = hs.Plan(n, P, Q, G, b, M, prec=prec)
+    ws2 = second.workspace()
+    for g in range(nout // 2, nout):
+        second.outer_update(g, A, B, C, ws=ws2)
+    torch.cuda.synchronize()
+    second.close()
+    assert torch.equal(C, ref)
