@@ -15,6 +15,8 @@
 #include <mutex>
 #include <new>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.h"
 #include "split.h"
 
@@ -340,10 +342,22 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   return HSUMMA_OK;
 }
 
+// A named range per outer step (host side: it brackets the launches, which
+// run asynchronously) for tools that trace roctx markers.
+struct StepRange {
+  explicit StepRange(int64_t g) {
+    char name[48];
+    std::snprintf(name, sizeof(name), "hsumma outer step %lld", (long long)g);
+    roctxRangePushA(name);
+  }
+  ~StepRange() { roctxRangePop(); }
+};
+
 int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
                double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
   const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
   for (int64_t g = 0; g < nouter; ++g) {
+    StepRange range(g);
     int rc = launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[g], p->outer_lo[g + 1],
                           g == 0 ? 1 : 0, g, ws, ws_bytes, stream);
     if (rc) return rc;
@@ -569,6 +583,7 @@ int hsumma_outer_update(hsumma_plan_t p, int64_t outer, const double* A, int64_t
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
   if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
+  StepRange range(outer);
   return launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1], 0,
                       outer, ws, ws_bytes, (hipStream_t)stream);
 }
