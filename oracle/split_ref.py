@@ -5,7 +5,7 @@ by products of small-integer "digit" matrices in the spirit of the error-free
 splitting of Ozaki, Ogita, Oishi and Rump ("Error-free transformations of
 matrix multiplication by using fast routines of matrix multiplication and its
 applications", Numer. Algorithms 59, 2012).  The rule written here is this
-project's reading of that method for BF16 / FP8-e4m3 digit planes:
+project's reading of that method for BF16 / FP8-e4m3 / INT8 digit planes:
 
   * Per outer panel (the M-wide k-range of one outer step), each row i of the
     A panel gets the exponent e_i = smallest integer with max_l |a_il| <= 2^e_i
@@ -15,7 +15,15 @@ project's reading of that method for BF16 / FP8-e4m3 digit planes:
     r_l = r_{l-1} * 2^t - d_l (r_0 = x, first shift h), with rint = round half
     to even.  BF16 uses h = 8, t = 9; FP8-e4m3 uses h = 4, t = 5, so every
     digit is an integer with |d| <= 2^h (256 or 16), exactly representable in
-    the narrow format.  Every step is exact in binary64.
+    the narrow format.  INT8 uses h = 6, t = 8: the rounded digits lie in
+    [-64, 64] (first) and [-128, 128] (later), and a carry pass over the s
+    digits, from the last to the second, replaces a digit of 128 (or 129
+    after a carry) by itself minus 256 and adds one to the digit before it.
+    That keeps the value (256 units of digit l are one unit of digit l - 1)
+    and the remainder, and leaves every later digit in [-128, 127] and the
+    first in [-64, 65]: the range of int8.  The carries depend on s, so the
+    first planes of an s-digit split can differ from a shorter split's.
+    Every step is exact in binary64.
   * a = 2^e * (sum_{l<=s} d_l 2^-(h + t(l-1)) + r_s 2^-(h + t(s-1))) exactly,
     with |r_s| <= 1/2.
   * The product keeps the digit pairs (l1, l2) with l1 + l2 <= s + 1; pair
@@ -44,7 +52,8 @@ from fractions import Fraction
 
 import numpy as np
 
-FORMATS = {"bf16": (8, 9), "e4m3": (4, 5)}
+FORMATS = {"bf16": (8, 9), "e4m3": (4, 5), "int8": (6, 8)}
+CARRY = {"int8"}                        # formats whose digits take the carry pass
 
 
 def exponents(X, axis: int) -> np.ndarray:
@@ -73,6 +82,11 @@ def digits(X, e, s: int, fmt: str, axis: int) -> np.ndarray:
         out[l] = d
         r = y - d                       # exact: the fraction bits of y
         shift = t
+    if fmt in CARRY:
+        for l in range(s - 1, 0, -1):
+            over = out[l] >= 128
+            out[l] = np.where(over, out[l] - 256, out[l])
+            out[l - 1] = out[l - 1] + over
     return out
 
 
