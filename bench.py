@@ -11,12 +11,12 @@ inner block b = 256, outer block M = 1024 (= n/Q, the widest outer panel
 owned by one processor column), entries u * 2^e with u ~ U[-1, 1] and
 e = rint(N(0, sigma^2 = 4)) (seeded, synthetic).
 
-Paths timed: FP64-MFMA, and the BF16 digit split (slice count chosen per
-panel) -- both FP64-accurate (checked on sampled entries against the Dot2
-oracle: max |c_hat - c| / (|A||B|)_ij <= 1e-14) -- the FP8-e4m3 split
-(reported, not FP64-accurate), and the BF16 split once more on entries
-u ~ U[-1, 1] (`bf16_uniform`: fewer slices suffice there).  `value` is the
-FP64-accurate GFLOP/s (2 n^3 / t) of the fastest accurate path on the
+Paths timed: FP64-MFMA, and the BF16 and INT8 digit splits (slice count
+chosen per panel) -- all FP64-accurate (checked on sampled entries against
+the Dot2 oracle: max |c_hat - c| / (|A||B|)_ij <= 1e-14) -- the FP8-e4m3
+split (reported, not FP64-accurate), and the BF16 and INT8 splits once more
+on entries u ~ U[-1, 1] (`*_uniform`: fewer slices suffice there).  `value`
+is the FP64-accurate GFLOP/s (2 n^3 / t) of the fastest accurate path on the
 workload's own entries; `paths` holds every path.
 
 `roofline` describes the dominant kernel of the reported path: its
@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 MFMA
 PEAK_BF16 = 2516.6    # TFLOP/s, dense BF16 MFMA
 PEAK_FP8 = 5033.2     # TFLOP/s, dense FP8 MFMA
+PEAK_INT8 = 5033.2    # TOP/s, dense INT8 MFMA
 GATE = 1e-14
 
 
@@ -63,7 +64,7 @@ def parse():
     ap.add_argument("--b", type=int, default=256)
     ap.add_argument("--M", type=int, default=1024)
     ap.add_argument("--sigma", type=float, default=2.0)
-    ap.add_argument("--paths", type=str, default="fp64,bf16,fp8,bf16_uniform")
+    ap.add_argument("--paths", type=str, default="fp64,bf16,int8,fp8,bf16_uniform,int8_uniform")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--samples", type=int, default=512)
@@ -183,7 +184,8 @@ def main():
         base = name.split("_")[0]
         sigma = 0.0 if name.endswith("_uniform") else args.sigma
         _, _, pA, pB, pcref, psref = operands(sigma)
-        prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16, "fp8": hs.SPLIT_FP8}[base]
+        prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16, "fp8": hs.SPLIT_FP8,
+                "int8": hs.SPLIT_INT8}[base]
         opts = {} if base != "fp8" else {"slices": 7}
         plan = hs.Plan(n, P, Q, G, b, M, prec=prec, **opts)
         ws = plan.workspace()
@@ -229,18 +231,20 @@ def main():
             pms = time_region(prod, max(3, args.steps), stream)
             w = n - last * M
             per_launch = pairs * 2.0 * n * n * w
-            peak = PEAK_BF16 if base == "bf16" else PEAK_FP8
+            peak = {"bf16": PEAK_BF16, "fp8": PEAK_FP8, "int8": PEAK_INT8}[base]
             ach = per_launch / (pms * 1e-3) / 1e12
-            kern = "slice_bf16_kernel" if base == "bf16" else "slice_fp8_kernel"
+            kern = {"bf16": "slice_bf16_kernel", "fp8": "slice_fp8_kernel",
+                    "int8": "slice_i8_kernel"}[base]
+            split_src = source_hash("k_split.hip", "split.h", "internal.h", "api.hip")
             rec.update({"slices": sorted(set(sl)), "pairs": pairs,
-                        "fp64_accurate": base == "bf16" and scaled <= GATE,
-                        "dtype": "bf16" if base == "bf16" else "fp8-e4m3",
+                        "fp64_accurate": base != "fp8" and scaled <= GATE,
+                        "dtype": {"bf16": "bf16", "fp8": "fp8-e4m3", "int8": "i8"}[base],
                         "mfma_util": round(pairs * flops / (ms * 1e-3) / 1e12 / peak, 4)})
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak,
-                               "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                               "traffic": (committed_traffic("slice_bf16", wl,
-                                                             source_hash("k_split.hip", "split.h", "internal.h", "api.hip"))
-                                           if name == "bf16" else None),
+                               "unit": "TOP/s" if base == "int8" else "TFLOP/s",
+                               "frac": round(ach / peak, 4),
+                               "traffic": (committed_traffic("slice_" + base, wl, split_src)
+                                           if name in ("bf16", "int8") else None),
                                "kernel": kern,
                                "flops_per_launch": per_launch, "launches_per_step": nouter,
                                "avg_launch_ms": round(pms, 4)}
@@ -266,7 +270,8 @@ def main():
         "vs_baseline": None,
         "dtype": head["dtype"],
         "data": "synthetic",
-        "path": {"fp64": "fp64-mfma", "bf16": "split-bf16", "fp8": "split-fp8"}[best.split("_")[0]],
+        "path": {"fp64": "fp64-mfma", "bf16": "split-bf16", "fp8": "split-fp8",
+                 "int8": "split-int8"}[best.split("_")[0]],
         "config": {"workload": "HSUMMA local updates, n=%d FP64, %dx%d grid, G=%d, b=%d, M=%d, "
                                "entries u*2^rint(N(0,%g)), u~U[-1,1]" % (n, P, Q, G, b, M,
                                                                            args.sigma ** 2),

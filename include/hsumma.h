@@ -61,7 +61,9 @@ typedef enum {
 typedef enum {
   HSUMMA_FP64 = 0,         /* FP64 MFMA local update */
   HSUMMA_SPLIT_BF16 = 1,   /* digit split into BF16 slices, FP32-exact MFMA, FP64 recombination */
-  HSUMMA_SPLIT_FP8 = 2     /* the same with FP8-e4m3 slices */
+  HSUMMA_SPLIT_FP8 = 2,    /* the same with FP8-e4m3 slices */
+  HSUMMA_SPLIT_INT8 = 3    /* the same with INT8 slices, INT32-exact MFMA (32 k per
+                              instruction, twice the BF16 rate); M <= 8192 */
 } hsumma_precision;
 
 typedef enum {
@@ -77,7 +79,7 @@ typedef struct {
   int64_t nb;         /* block-cyclic block size; 0 => b                        */
   int32_t slices;     /* split forms: digits per operand, 0 => chosen per panel */
   int32_t min_slices; /* bounds of the per-panel choice; 0 => 3                 */
-  int32_t max_slices; /*                                   0 => 7               */
+  int32_t max_slices; /*                     0 => 7 (BF16, FP8) or 8 (INT8)    */
   int32_t tile_m;     /* macro-tile rows;  0 => default / tuned                 */
   int32_t tile_n;     /* macro-tile cols;  0 => default / tuned                 */
   int32_t kc;         /* k-chunk staged per LDS buffer; 0 => default            */
@@ -87,7 +89,8 @@ typedef struct {
                       /* whose modelled max error relative to (|A||B|)_ij is    */
                       /* <= 2^-tau_bits (model: bits(s) against the panel's     */
                       /* value spread and k; max_slices when the spread         */
-                      /* statistic is saturated by a narrow panel); 0 => 48     */
+                      /* statistic is saturated by a narrow panel);             */
+                      /* 0 => 48 (50 for INT8)                                  */
   int32_t staged;     /* FP64 path: 1 = always the register-staged kernel,      */
                       /* 0 = direct-to-LDS loads where alignment allows         */
   int32_t reserved[4];
@@ -174,7 +177,7 @@ int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, voi
 /*
  * Layout of the split forms' workspace after a call: byte offsets of the A
  * digit planes (planes x m x Wp digits, 2 B per BF16 digit or 1 B per
- * FP8-e4m3 digit, stored k16-block-major: digit (plane, row, k) at
+ * FP8-e4m3 or INT8 digit, stored k16-block-major: digit (plane, row, k) at
  * plane*m*Wp + (k/16)*m*16 + row*16 + k%16), the B digit planes (the same
  * with n columns: B transposed), the int32 row exponents of A and column
  * exponents of B.  They hold the most recently split panel; of its planes
@@ -190,9 +193,11 @@ int hsumma_split_layout(hsumma_plan_t plan, size_t* off_digA, size_t* off_digB,
  * d (32 x 32 FP32, row-major) = a (32 x k digits, row-major) x b (k x 32
  * digits, row-major) by chained 32x32x16 MFMAs (the slice kernels'
  * instructions) with FP32 accumulation, fmt 0 = BF16 bit patterns (2 B),
- * 1 = FP8-e4m3 bytes.  k a positive multiple of 16.  Integer digits whose
- * partial sums stay within 2^24 must come back exact.  All pointers are
- * device memory; asynchronous on `stream`.
+ * 1 = FP8-e4m3 bytes; fmt 2 = INT8 bytes by 32x32x32 MFMAs with INT32
+ * accumulation, returned converted to FP32.  k a positive multiple of 16
+ * (32 for INT8).  Integer digits whose partial sums stay within 2^24 must
+ * come back exact.  All pointers are device memory; asynchronous on
+ * `stream`.
  */
 int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k, float* d,
                             void* stream);

@@ -81,10 +81,10 @@ struct hsumma_plan_s {
   int32_t per_xcd = 0;
   bool items_even = false;     // every work item starts at an even column, has even width
   // precision form: workspace layout (byte offsets) and panel geometry
-  int32_t fmt = -1;            // -1: FP64 path; 0: BF16 digits; 1: FP8-e4m3 digits
+  int32_t fmt = -1;            // -1: FP64 path; 0: BF16, 1: FP8-e4m3, 2: INT8 digits
   int32_t Wp = 0;              // padded panel width
   size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_stats = 0, off_slices = 0,
-         ws_bytes = 0;
+         off_dump = 0, ws_bytes = 0;
   std::map<int, DeviceState> dev;
   std::mutex mu;
   bool have_graph = false;
@@ -298,7 +298,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   hs::SplitArgs sa;
   sa.A = A; sa.lda = lda; sa.B = B; sa.ldb = ldb;
   sa.m = (int32_t)p->m; sa.n = (int32_t)p->n; sa.k0 = (int32_t)k0; sa.w = (int32_t)(k1 - k0);
-  const int64_t pad = p->fmt == 0 ? 64 : hs::kSplitChunk;
+  const int64_t pad = p->fmt == 1 ? hs::kSplitChunk : 64;
   sa.Wp = (int32_t)(((k1 - k0) + pad - 1) / pad * pad);
   sa.fmt = p->fmt;
   sa.smax = p->opts.max_slices;
@@ -334,6 +334,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   la.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
   la.log2w = sa.log2w;
   la.zero_init = zero_init; la.persistent = persistent ? 1 : 0;
+  la.dump = (double*)(w8 + p->off_dump);
   e = hs::launch_slices(p->fmt, la, grid, stream);
   if (e != hipSuccess) {
     set_error(std::string("slice products launch: ") + hipGetErrorString(e));
@@ -397,7 +398,8 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   if (M % b) return invalid("outer block M must be a multiple of b");
   if (o.dist != HSUMMA_DIST_BLOCK && o.dist != HSUMMA_DIST_BLOCK_CYCLIC)
     return invalid("unknown distribution");
-  if (o.prec != HSUMMA_FP64 && o.prec != HSUMMA_SPLIT_BF16 && o.prec != HSUMMA_SPLIT_FP8)
+  if (o.prec != HSUMMA_FP64 && o.prec != HSUMMA_SPLIT_BF16 && o.prec != HSUMMA_SPLIT_FP8 &&
+      o.prec != HSUMMA_SPLIT_INT8)
     return invalid("unknown precision");
   if (o.nb < 0) return invalid("nb must be >= 0");
   int I = 0, J = 0;
@@ -425,30 +427,38 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     }
     p->cfg = cfg;
   } else {
-    p->fmt = o.prec == HSUMMA_SPLIT_BF16 ? 0 : 1;
-    // both forms: 64 x 128 macro-tiles streamed in 16-k steps
-    const hs::TileCfg scfg{64, 128, 16};
+    p->fmt = o.prec == HSUMMA_SPLIT_BF16 ? 0 : o.prec == HSUMMA_SPLIT_FP8 ? 1 : 2;
+    // every form: 64 x 128 macro-tiles streamed in 16-k steps (32-k for INT8)
+    const hs::TileCfg scfg{64, 128, p->fmt == 2 ? 32 : 16};
     if ((o.tile_m && o.tile_m != scfg.tm) || (o.tile_n && o.tile_n != scfg.tn) ||
         (o.kc && o.kc != scfg.kc)) {
       delete p;
-      return invalid("split forms use fixed 64 x 128 macro-tiles and 16-k steps");
+      return invalid("split forms use fixed 64 x 128 macro-tiles and 16-k steps (32-k for INT8)");
     }
     p->cfg = scfg;
+    const int slim = hs::split_max_slices(p->fmt);
     if (!p->opts.min_slices) p->opts.min_slices = 3;
-    if (!p->opts.max_slices) p->opts.max_slices = hs::kSplitMaxSlices;
-    if (!p->opts.tau_bits) p->opts.tau_bits = 48;
+    if (!p->opts.max_slices) p->opts.max_slices = slim;
+    // INT8 digits drop more of the product at a given bit count than BF16
+    // ones (more, larger digit pairs beyond the kept levels): two more bits
+    if (!p->opts.tau_bits) p->opts.tau_bits = p->fmt == 2 ? 50 : 48;
     const int smin = p->opts.min_slices, smax = p->opts.max_slices, sf = p->opts.slices;
-    if (smin < 1 || smax > hs::kSplitMaxSlices || smin > smax || sf < 0 ||
-        sf > hs::kSplitMaxSlices) {
+    if (smin < 1 || smax > slim || smin > smax || sf < 0 || sf > slim) {
       delete p;
-      return invalid("slice counts must satisfy 1 <= min_slices <= max_slices <= 7, slices <= 7");
+      return invalid(slim == 8 ? "slice counts must satisfy 1 <= min_slices <= max_slices <= 8, slices <= 8"
+                               : "slice counts must satisfy 1 <= min_slices <= max_slices <= 7, slices <= 7");
     }
     if (sf > smax) p->opts.max_slices = sf;
     if (p->fmt == 1 && M > 8192) {
       delete p;
       return invalid("FP8 split form needs M <= 8192 (exact FP32 accumulation over a panel)");
     }
-    const int64_t pad = p->fmt == 0 ? 64 : hs::kSplitChunk;   // BF16 steps in groups of 64 k
+    if (p->fmt == 2 && M > 8192) {
+      delete p;
+      return invalid("INT8 split form needs M <= 8192 (exact INT32 accumulation over a panel)");
+    }
+    // BF16 steps in groups of 64 k, INT8 in pairs of 32-k steps
+    const int64_t pad = p->fmt == 1 ? hs::kSplitChunk : 64;
     const int64_t Wp = (M + pad - 1) / pad * pad;
     p->Wp = (int32_t)Wp;
     const int64_t esz = p->fmt == 0 ? 2 : 1;
@@ -468,6 +478,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     p->off_fB = off; off = al(off + (size_t)n * 4);
     p->off_stats = off; off = al(off + (size_t)std::max<int64_t>(1, nout) * 8);
     p->off_slices = off; off = al(off + (size_t)std::max<int64_t>(1, nout) * 4);
+    p->off_dump = off; off = al(off + 64 * sizeof(double));
     p->ws_bytes = off;
   }
 
@@ -682,9 +693,10 @@ int hsumma_split_layout(hsumma_plan_t p, size_t* off_digA, size_t* off_digB, siz
 
 int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k, float* d,
                             void* stream) {
-  if (fmt != 0 && fmt != 1) return invalid("fmt must be 0 (BF16) or 1 (FP8-e4m3)");
+  if (fmt != 0 && fmt != 1 && fmt != 2) return invalid("fmt must be 0 (BF16), 1 (FP8-e4m3) or 2 (INT8)");
   if (!a || !b || !d) return invalid("null pointer");
-  if (k < 16 || k % 16) return invalid("k must be a positive multiple of 16");
+  if (fmt == 2 ? (k < 32 || k % 32) : (k < 16 || k % 16))
+    return invalid("k must be a positive multiple of 16 (32 for INT8)");
   hipError_t e = hs::launch_mfma_probe(fmt, a, b, k, d, (hipStream_t)stream);
   if (e != hipSuccess) {
     set_error(std::string("probe launch: ") + hipGetErrorString(e));

@@ -1,7 +1,7 @@
 // Precision form of the local update: FP64 operands split into small-integer
-// digit planes (BF16 or FP8-e4m3), products of the planes on the matrix
-// cores with FP32 accumulation that is exact by construction, and FP64
-// recombination.  An error-free splitting in the spirit of Ozaki, Ogita,
+// digit planes (BF16, FP8-e4m3 or INT8), products of the planes on the matrix
+// cores with FP32 (INT32) accumulation that is exact by construction, and
+// FP64 recombination.  An error-free splitting in the spirit of Ozaki, Ogita,
 // Oishi and Rump (Numer. Algorithms 59, 2012); not part of the HSUMMA paper,
 // which only fixes the update C += A_panel x B_panel being computed.
 //
@@ -11,7 +11,11 @@
 //   x    = a 2^-e in [-1, 1];  d_1 = rint(x 2^H), r_1 = x 2^H - d_1,
 //          d_l = rint(r_{l-1} 2^T), r_l = r_{l-1} 2^T - d_l   (round half even)
 //   BF16: H = 8, T = 9; FP8-e4m3: H = 4, T = 5; every |d| <= 2^H, exact in
-//   the narrow format.  BF16 planes hold d_l 2^(-T (l-1)) (a power-of-two
+//   the narrow format.  INT8: H = 6, T = 8 (digits in [-64, 64] and
+//   [-128, 128]), then a carry pass from the last of the s digits to the
+//   second turns a digit of 128 (129 after a carry) into itself minus 256
+//   with one added to the digit before it: same value, every later digit in
+//   [-128, 127], the first in [-64, 65].  BF16 planes hold d_l 2^(-T (l-1)) (a power-of-two
 //   scale, still exact) so that the product of planes l1 and l2 already
 //   carries its weight 2^(-T (l1 + l2 - 2)).
 //
@@ -24,6 +28,8 @@
 // bound (every 64 or 128 k).  FP8: every
 // level is exact over the whole panel (7 pairs x 2^8 x w <= 2^24 for
 // w <= 9362) and is added, scaled by 2^(-T (L - 2)), at the end of the panel.
+// INT8: every level is exact in INT32 over the whole panel (8 pairs x 2^14 x
+// w < 2^31 for w <= 8192) and is added the same way.
 // Finally C += 2^(e_i + f_j - 2H) x panel sum, in FP64.
 #include <type_traits>
 
@@ -35,6 +41,51 @@ namespace hs {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+
+// digit format FMT (0: BF16, 1: FP8-e4m3, 2: INT8): first shift H, later
+// shift T, bytes per stored digit
+constexpr int digit_h(int fmt) { return fmt == 0 ? 8 : fmt == 1 ? 4 : 6; }
+constexpr int digit_t(int fmt) { return fmt == 0 ? 9 : fmt == 1 ? 5 : 8; }
+constexpr int digit_bytes(int fmt) { return fmt == 0 ? 2 : 1; }
+
+// INT8 digits of the 16 values r[] (already scaled by 2^-e): s digits per
+// value (round half to even), then the carry pass into the int8 range;
+// plane l's 16 bytes are packed into w[l][0..3].
+__device__ __forceinline__ void int8_digits(const double* r, int s,
+                                            uint32_t (&w)[kSplitMaxSlices][4]) {
+#pragma unroll
+  for (int l = 0; l < kSplitMaxSlices; ++l)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[l][j] = 0u;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    int c[kSplitMaxSlices];
+    double x = r[q];
+    int shift = digit_h(2);
+#pragma unroll
+    for (int l = 0; l < kSplitMaxSlices; ++l) {
+      c[l] = 0;
+      if (l < s) {
+        const double y = ldexp(x, shift);
+        const double d = rint(y);
+        x = y - d;
+        c[l] = (int)d;
+        shift = digit_t(2);
+      }
+    }
+#pragma unroll
+    for (int l = kSplitMaxSlices - 1; l >= 1; --l)
+      if (l < s && c[l] >= 128) {
+        c[l] -= 256;
+        c[l - 1] += 1;
+      }
+#pragma unroll
+    for (int l = 0; l < kSplitMaxSlices; ++l)
+      w[l][q >> 2] |= (uint32_t)(uint8_t)(int8_t)c[l] << (8 * (q & 3));
+  }
+}
 
 __device__ inline int exponent_bound(double mx) {
   if (!(mx > 0.0)) return 0;
@@ -59,6 +110,7 @@ __device__ inline uint8_t e4m3_of_int(int d) {
 // plane * plane_stride + (kk / 16) * rows * 16 + row * 16 + kk % 16, so that
 // the 16 k of one row of one block are contiguous and one block of a plane
 // (all rows) is one contiguous run, the unit the product kernel streams.
+// INT8 digits are stored as their two's-complement bytes.
 
 // Slice count of a panel from its statistics.  ka, kb: log2 of the largest
 // kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
@@ -223,9 +275,7 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs
 
 template <int FMT, bool COLS>
 __device__ void split_digit_lines(const SplitArgs& p, int blk, int s) {
-  constexpr int H = FMT == 0 ? 8 : 4;
-  constexpr int T = FMT == 0 ? 9 : 5;
-  constexpr int ESZ = FMT == 0 ? 2 : 1;
+  constexpr int H = digit_h(FMT), T = digit_t(FMT), ESZ = digit_bytes(FMT);
   constexpr int NW = kSplitWaves;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nl = COLS ? p.n : p.m;
@@ -249,6 +299,14 @@ __device__ void split_digit_lines(const SplitArgs& p, int blk, int s) {
     for (int q = 0; q < 16; ++q) r[q] = ldexp(x[q], -e);
     if (k0 + 16 * NW < p.Wp) load(x, k0 + 16 * NW);
     const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
+    if (FMT == 2) {
+      uint32_t w[kSplitMaxSlices][4];
+      int8_digits(r, s, w);
+#pragma unroll
+      for (int l = 0; l < kSplitMaxSlices; ++l)
+        if (l < s) *(uint4*)(dig + l * plane + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
+      continue;
+    }
     int shift = H;
     for (int l = 0; l < s; ++l) {
       uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
@@ -278,9 +336,7 @@ constexpr int kTileStride = 18;              // doubles per staged row
 
 template <int FMT>
 __device__ void split_digit_rows(const SplitArgs& p, int blk, int s, double* tile) {
-  constexpr int H = FMT == 0 ? 8 : 4;
-  constexpr int T = FMT == 0 ? 9 : 5;
-  constexpr int ESZ = FMT == 0 ? 2 : 1;
+  constexpr int H = digit_h(FMT), T = digit_t(FMT), ESZ = digit_bytes(FMT);
   constexpr int NW = kSplitWaves;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = blk * 64 + lane;
@@ -313,7 +369,15 @@ __device__ void split_digit_rows(const SplitArgs& p, int blk, int s, double* til
 #pragma unroll
     for (int q = 0; q < 16; ++q) r[q] = ldexp(tile[lane * kTileStride + q], -e);
     if (k0 + 16 * NW < p.Wp) load(k0 + 16 * NW);
-    if (valid) {
+    if (valid && FMT == 2) {
+      const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
+      uint32_t w[kSplitMaxSlices][4];
+      int8_digits(r, s, w);
+#pragma unroll
+      for (int l = 0; l < kSplitMaxSlices; ++l)
+        if (l < s)
+          *(uint4*)(dig + l * p.planeA + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
+    } else if (valid) {
       const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
       int shift = H;
       for (int l = 0; l < s; ++l) {
@@ -341,7 +405,7 @@ template <int FMT>
 __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArgs p) {
   __shared__ double tiles[kSplitWaves][64 * kTileStride];
   const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w,
-                             FMT == 0 ? 8 : 4, FMT == 0 ? 9 : 5);
+                             digit_h(FMT), digit_t(FMT));
   const int ga = (p.m + 63) / 64;
   if ((int)blockIdx.x < ga) split_digit_rows<FMT>(p, blockIdx.x, s, tiles[threadIdx.x >> 6]);
   else split_digit_lines<FMT, true>(p, blockIdx.x - ga, s);
@@ -871,16 +935,321 @@ __global__ __launch_bounds__(256, 1) void slice_fp8_kernel(SliceArgs p) {
   }
 }
 
+// ---- INT8 slice products, streamed ------------------------------------------
+// The BF16 kernel's data flow on INT8 digits and v_mfma_i32_32x32x32_i8: lane
+// l holds A[l % 32][16 (l / 32) .. + 15] and B[16 (l / 32) .. + 15][l % 32]
+// (16 bytes each), D item v of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4]
+// [l % 32] in INT32.  On gfx950 the instruction issues in the time of the
+// 16-k BF16 one from the same 16 bytes per lane, so it does twice the k per
+// clock; a 32-k step of a plane is the BF16 step's 64 x 32 bytes of A and
+// 128 x 32 bytes of B, with the same LDS image, swizzle, ring and DMA
+// deal over the waves.  The planes are stored k16-block-major (as the FP8
+// ones): a 32-k step kb is k16 blocks 2 kb (half 0) and 2 kb + 1 (half 1),
+// so the 16-byte unit (row, half) of the step sits at row x 16 + half x rows
+// x 16 past the step's base.  Every level of digit pairs stays exact in INT32
+// over a whole panel (at most 8 pairs of |d d'| <= 2^14 per k, panels of at
+// most 8192 k), so each level keeps one accumulator from the item's first
+// step to its last, with no restarts, and the levels are added into FP64
+// once, scaled by 2^(-8 a), smallest weight first.
+// Wait until at most k x PER + EXTRA of this wave's vector-memory
+// instructions are outstanding (k <= KMAX at run time; the count is an
+// immediate, capped at the counter's 63).
+template <int PER, int KMAX, int EXTRA>
+__device__ __forceinline__ void vm_wait_steps_plus(int k) {
+  if (KMAX >= 4 && k >= 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 4 * PER + EXTRA)) : "memory");
+  else if (KMAX >= 3 && k == 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 3 * PER + EXTRA)) : "memory");
+  else if (KMAX >= 2 && k == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 2 * PER + EXTRA)) : "memory");
+  else if (KMAX >= 1 && k == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, PER + EXTRA)) : "memory");
+  else asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, EXTRA)) : "memory");
+}
+
+template <int S>
+__device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem) {
+  constexpr int TM = kBf16TM, TN = kBf16TN, NS = bf16_stages(S);
+  constexpr int ABYTES = S * TM * 32, BBYTES = S * TN * 32, SB = ABYTES + BBYTES;
+  // DMA wave-instructions per 32-k step of waves 0-1 and 2-3
+  constexpr int NIHI = 3 * (S / 2) + (S & 1 ? 2 : 0), NILO = 3 * (S / 2) + (S & 1);
+  constexpr int LAG = S < 3 ? S : (S <= 5 ? 2 : 3);
+  constexpr int NSTORE = 32;                    // C stores per lane and item (2 x 16)
+  static_assert(NS >= 3 && NS * SB <= kBf16Lds, "LDS ring");
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+  const int wm = wave >> 1, wn = wave & 1;
+  const bool hi = wave < 2;                     // this wave issues NIHI per step
+  // Per-lane offsets are derived from a lane id read where they are needed,
+  // opaque to the compiler (v_mbcnt): derived once, they stay live across
+  // the epilogue, where 8 levels of accumulators leave no room, and their
+  // reloads from scratch would wait for the epilogue's writes.
+  auto lane_id = [] {
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+  };
+
+  const __amdgpu_buffer_rsrc_t rsrcA =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.digA, (short)0, (int)p.bytesA, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rsrcB =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.digB, (short)0, (int)p.bytesB, kBufferWord3);
+  const uint32_t kbA = (uint32_t)p.rowsA * 32u, kbB = (uint32_t)p.rowsB * 32u;  // bytes per 32-k step
+  const uint32_t halfA = (uint32_t)p.rowsA * 16u, halfB = (uint32_t)p.rowsB * 16u;
+  const uint32_t planeAB = (uint32_t)p.planeA, planeBB = (uint32_t)p.planeB;   // one byte per digit
+  const int nsteps = p.Wp / 32;                // even: the panel is padded to 64 k
+  // LDS byte offsets of this lane's A and B fragments (rows / columns
+  // 32 wm + l % 32 and 64 wn + l % 32, half l / 32, swizzled)
+  auto frag_offsets = [&](int& aoff, int& boff) {
+    const int l = lane_id(), l32 = l & 31, lh = l >> 5;
+    const int arow = wm * 32 + l32, bcol = wn * 64 + l32;
+    aoff = (arow * 2 + (lh ^ ((arow >> 3) & 1))) * 16;
+    boff = (bcol * 2 + (lh ^ ((bcol >> 3) & 1))) * 16;
+  };
+
+  const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
+  const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
+  // the work item of the k-th slot of this workgroup, or -1
+  auto item_index = [&](int slot) {
+    if (!p.persistent && slot != slot0) return -1;
+    if (slot >= p.per_xcd) return -1;
+    const int idx = xcd * p.per_xcd + slot;
+    return idx < p.nitems ? idx : -1;
+  };
+
+  // the BF16 kernel's deal of LDS units over the waves; only the global
+  // offset of a unit differs (ragged rows and columns clamped)
+  uint32_t voffA = 0, voffB = 0;
+  auto set_dma_offsets = [&](const WorkItem& w) {
+    const int l = lane_id();
+    const int ua = (wave & 1) * 64 + l;
+    const int rowa = ua >> 1, halfa = (ua & 1) ^ ((rowa >> 3) & 1);
+    const int ub = wave * 64 + l;
+    const int colb = ub >> 1, halfb = (ub & 1) ^ ((colb >> 3) & 1);
+    voffA = (uint32_t)(w.r0 + min(rowa, w.h - 1)) * 16u + halfa * halfA;
+    voffB = (uint32_t)(w.c0 + min(colb, w.w - 1)) * 16u + halfb * halfB;
+  };
+  auto dmaA = [&](int plane, int kb, uint8_t* dst) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrcA, (__attribute__((address_space(3))) void*)dst, 16,
+                                             voffA, (uint32_t)(plane * planeAB + kb * kbA), 0, 0);
+  };
+  auto dmaB = [&](int plane, int kb, uint8_t* dst) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrcB, (__attribute__((address_space(3))) void*)dst, 16,
+                                             voffB, (uint32_t)(plane * planeBB + kb * kbB), 0, 0);
+  };
+  auto issue = [&](int kb, int st) {
+    uint8_t* stage = smem + st * SB;
+#pragma unroll
+    for (int l = 0; l + 1 < S; l += 2) {
+      const int pa = l + (wave >> 1);
+      dmaA(pa, kb, stage + pa * (TM * 32) + (wave & 1) * 1024);
+      dmaB(l, kb, stage + ABYTES + l * (TN * 32) + wave * 1024);
+      dmaB(l + 1, kb, stage + ABYTES + (l + 1) * (TN * 32) + wave * 1024);
+    }
+    if (S & 1) {
+      if (wave < 2) dmaA(S - 1, kb, stage + (S - 1) * (TM * 32) + wave * 1024);
+      dmaB(S - 1, kb, stage + ABYTES + (S - 1) * (TN * 32) + wave * 1024);
+    }
+  };
+  auto wait_step = [&](int later) {
+    if (hi) vm_wait_steps<NIHI, NS - 1>(later);
+    else vm_wait_steps<NILO, NS - 1>(later);
+  };
+
+  int idx = item_index(slot0);
+  if (idx < 0) return;
+  WorkItem it = p.items[idx];
+  set_dma_offsets(it);
+  i4v fa[2][S], fb0[2][S], fb1[2][S];          // fragments, two register sets
+  int aoff, boff;
+  auto read_row = [&](int set, int st, int r) {
+    const uint8_t* sA = smem + st * SB;
+    const uint8_t* sB = sA + ABYTES;
+    fa[set][S - 1 - r] = *(const i4v*)(sA + (S - 1 - r) * (TM * 32) + aoff);
+    fb0[set][r] = *(const i4v*)(sB + r * (TN * 32) + boff);
+    fb1[set][r] = *(const i4v*)(sB + r * (TN * 32) + boff + 1024);
+  };
+  // the first item's prologue: NS steps in flight, step 0 landed, the first
+  // LAG rows of fragments read
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+    if (st < nsteps) issue(st, st);
+  wait_step(min(NS - 1, nsteps - 1));
+  ring_barrier();
+  frag_offsets(aoff, boff);
+#pragma unroll
+  for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
+
+  for (int slot = slot0; idx >= 0; slot += slots) {
+    i16v acc0[S], acc1[S];                     // level accumulators, blocks 0 and 1
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      acc0[a] = i16v{};
+      acc1[a] = i16v{};
+    }
+
+    // rows r = 0 .. S-1 pair A fragment S-1-r with B fragments 0 .. r; reads
+    // run LAG rows ahead of the MFMAs (as in the BF16 kernel)
+    auto row = [&](int set, int r) {
+      const int l1 = S - 1 - r;
+#pragma unroll
+      for (int l2 = 0; l2 <= r; ++l2) {
+        const int a = l1 + l2;
+        acc0[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[set][l1], fb0[set][l2], acc0[a], 0, 0, 0);
+        acc1[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[set][l1], fb1[set][l2], acc1[a], 0, 0, 0);
+      }
+    };
+    // one 32-k step, with the BF16 kernel's barrier placement and refill
+    auto step = [&](int ci, int cur) {
+      const int nxt = cur ^ 1;
+      const bool more = ci + 1 < nsteps;
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        if (r == S - LAG && more) {
+          wait_step(min(NS - 2, nsteps - 2 - ci));   // step ci + 1 landed (this wave)
+          ring_barrier();
+          if (ci + NS < nsteps) issue(ci + NS, ci % NS);
+        }
+        if (r + LAG < S) read_row(cur, ci % NS, r + LAG);
+        else if (more) read_row(nxt, (ci + 1) % NS, r + LAG - S);
+        row(cur, r);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+
+    for (int ci = 0; ci < nsteps; ci += 2) {
+      step(ci, 0);
+      step(ci + 1, 1);
+    }
+
+    // Epilogue: (1) the exponent loads; (2) once every wave is done with the
+    // ring, the next item's first NS steps of DMA; (3) per C element the
+    // level sum, sum_a 2^(-8 a) level_a from the smallest weight up (Horner
+    // in 2^-8: every scaling is exact; taken before the DMA), and
+    // C += 2^(e_i + f_j - 12) x sum as
+    // an FP64 atomic add (the first panel of a product stores instead): the
+    // read of C happens in L2, no wave waits for it, and each C element gets
+    // exactly one add per launch, so the result is the single rounded sum a
+    // load and a store would give.  The next item's first wait leaves these
+    // NSTORE writes in flight.  The lane id is read again here, opaque to
+    // the compiler: derived from the kernel's lane id, the 16 row indices
+    // below are hoisted out of the item loop and spilled.
+    const int lane_e = lane_id();
+    const int le32 = lane_e & 31, leh = lane_e >> 5;
+    auto erow = [&](int v) { return wm * 32 + 8 * (v >> 2) + 4 * leh + (v & 3); };
+    int ea[16], fq[2];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) ea[v] = p.eA[it.r0 + min(erow(v), it.h - 1)];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) fq[q] = p.fB[it.c0 + min(wn * 64 + q * 32 + le32, it.w - 1)];
+    // the level sums before the DMA: that frees the accumulators, which at 8
+    // levels the register file needs
+    double cp0[16], cp1[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      cp0[v] = (double)acc0[S - 1][v];
+      cp1[v] = (double)acc1[S - 1][v];
+#pragma unroll
+      for (int a = S - 2; a >= 0; --a) {
+        cp0[v] = fma(cp0[v], 0x1p-8, (double)acc0[a][v]);
+        cp1[v] = fma(cp1[v], 0x1p-8, (double)acc1[a][v]);
+      }
+      // taken here: the compiler would otherwise sink some of the sums past
+      // the DMA, keeping (and spilling) their accumulators
+      asm volatile("" ::"v"(cp0[v]), "v"(cp1[v]));
+    }
+    // the exponents have landed before the DMA is issued (vmcnt(0), an
+    // S_WAITCNT the compiler sees), so that no wait for them after it can
+    // hold the DMA too
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_sched_barrier(0);
+    // every wave's reads of the ring have retired, and no DMA of this item is
+    // outstanding
+    ring_barrier();
+    const int nidx = __builtin_amdgcn_readfirstlane(item_index(slot + slots));
+    WorkItem nt = it;
+    if (nidx >= 0) {
+      nt = p.items[nidx];
+      set_dma_offsets(nt);
+#pragma unroll
+      for (int st = 0; st < NS; ++st)
+        if (st < nsteps) issue(st, st);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // Every lane issues all NSTORE writes: lanes outside a ragged item write
+    // to their own slot of the dump area, so that the count the next item's
+    // first wait allows for is exact.
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int col = wn * 64 + q * 32 + le32;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const double cp = q ? cp1[v] : cp0[v];
+        const int row = erow(v);
+        const double add = ldexp(cp, ea[v] + fq[q] - 12);
+        const bool in = row < it.h && col < it.w;
+        double* dst = in ? p.C + (int64_t)(it.r0 + row) * p.ldc + it.c0 + col : p.dump + lane_e;
+        if (p.zero_init) *dst = add;
+        else unsafeAtomicAdd(dst, add);
+      }
+    }
+    it = nt;
+    idx = nidx;
+    if (idx >= 0) {
+      // the next item's step 0 landed; its writes above are the newest
+      // NSTORE vector-memory instructions and need not have completed
+      if (hi) vm_wait_steps_plus<NIHI, NS - 1, NSTORE>(min(NS - 1, nsteps - 1));
+      else vm_wait_steps_plus<NILO, NS - 1, NSTORE>(min(NS - 1, nsteps - 1));
+      ring_barrier();
+      frag_offsets(aoff, boff);
+#pragma unroll
+      for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void slice_i8_kernel(SliceArgs p) {
+  __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
+  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w,
+                             digit_h(2), digit_t(2));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
+  switch (s) {
+    case 1: slice_i8_items<1>(p, smem); break;
+    case 2: slice_i8_items<2>(p, smem); break;
+    case 3: slice_i8_items<3>(p, smem); break;
+    case 4: slice_i8_items<4>(p, smem); break;
+    case 5: slice_i8_items<5>(p, smem); break;
+    case 6: slice_i8_items<6>(p, smem); break;
+    case 7: slice_i8_items<7>(p, smem); break;
+    default: slice_i8_items<8>(p, smem); break;
+  }
+}
+
 // ---- self-test of the matrix-core accumulation -------------------------------
 // D (32 x 32, FP32) = A (32 x k digits, row-major) x B (k x 32 digits,
 // row-major) by chained 32x32x16 MFMAs with FP32 accumulation -- the
 // instructions and operand layout of the slice-product kernels (lane l holds
 // A[l % 32][8 (l / 32) .. + 7] and B[8 (l / 32) .. + 7][l % 32]; D item v
-// of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]).  One wave.
+// of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]).  INT8 digits
+// (FMT 2) go through 32x32x32 MFMAs with INT32 accumulation (lane l holds
+// A[l % 32][16 (l / 32) .. + 15] and B[16 (l / 32) .. + 15][l % 32]), and D
+// is returned converted to FP32.  One wave.
 template <int FMT>
 __global__ __launch_bounds__(64) void mfma_probe_kernel(const void* a, const void* b, int k,
                                                          float* out) {
   const int l = threadIdx.x, l32 = l & 31, lh = l >> 5;
+  if (FMT == 2) {
+    const int8_t* A = (const int8_t*)a;
+    const int8_t* B = (const int8_t*)b;
+    i16v iacc = {};
+    for (int kc = 0; kc < k; kc += 32) {
+      i4v av = {}, bv = {};
+      for (int e = 0; e < 16; ++e) {
+        const int kk = kc + 16 * lh + e;
+        av[e >> 2] |= (int)(uint8_t)A[l32 * k + kk] << (8 * (e & 3));
+        bv[e >> 2] |= (int)(uint8_t)B[kk * 32 + l32] << (8 * (e & 3));
+      }
+      iacc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, iacc, 0, 0, 0);
+    }
+    for (int v = 0; v < 16; ++v) out[(8 * (v >> 2) + 4 * lh + (v & 3)) * 32 + l32] = (float)iacc[v];
+    return;
+  }
   f16v acc = {};
   for (int kc = 0; kc < k; kc += 16) {
     if (FMT == 0) {
@@ -912,8 +1281,10 @@ hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float
                              hipStream_t s) {
   if (fmt == 0)
     hipLaunchKernelGGL(mfma_probe_kernel<0>, dim3(1), dim3(64), 0, s, a, b, k, out);
-  else
+  else if (fmt == 1)
     hipLaunchKernelGGL(mfma_probe_kernel<1>, dim3(1), dim3(64), 0, s, a, b, k, out);
+  else
+    hipLaunchKernelGGL(mfma_probe_kernel<2>, dim3(1), dim3(64), 0, s, a, b, k, out);
   return hipGetLastError();
 }
 
@@ -923,8 +1294,10 @@ hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(split_stats_kernel, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
   if (a.fmt == 0)
     hipLaunchKernelGGL(split_digits_kernel<0>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
-  else
+  else if (a.fmt == 1)
     hipLaunchKernelGGL(split_digits_kernel<1>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+  else
+    hipLaunchKernelGGL(split_digits_kernel<2>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -937,8 +1310,10 @@ hipError_t launch_zero_u32(uint32_t* ptr, int n, hipStream_t s) {
 hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s) {
   if (fmt == 0)
     hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(256), 0, s, a);
-  else
+  else if (fmt == 1)
     hipLaunchKernelGGL(slice_fp8_kernel, dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(slice_i8_kernel, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -5,14 +5,16 @@
 
 namespace hs {
 
-constexpr int kSplitMaxSlices = 7;   // digit planes written per operand
+constexpr int kSplitMaxSlices = 8;   // digit planes written per operand (any format)
+// largest slice count of a format: 7 BF16 / FP8 digits, 8 INT8 digits
+constexpr int split_max_slices(int fmt) { return fmt == 2 ? 8 : 7; }
 constexpr int kSplitChunk = 32;      // panel width is padded to a multiple of this
 
 struct SplitArgs {
   const double* A; int64_t lda;      // panel = A(:, k0:k0+w)
   const double* B; int64_t ldb;      // panel = B(k0:k0+w, :)
   int32_t m, n, k0, w, Wp;           // Wp: padded panel width (multiple of kSplitChunk)
-  int32_t fmt;                       // 0: BF16 digits, 1: FP8-e4m3 digits
+  int32_t fmt;                       // 0: BF16 digits, 1: FP8-e4m3 digits, 2: INT8 digits
   int32_t smax;                      // planes to write
   void* digA; int64_t planeA;        // planes of m x Wp digits (elements per plane)
   void* digB; int64_t planeB;        // planes of n x Wp digits (B transposed)
@@ -35,6 +37,7 @@ struct SliceArgs {
   float log2k;                       // log2 of the product's inner dimension k
   float log2w;                       // log2 of the panel width
   int32_t zero_init, persistent;
+  double* dump;                      // 64 doubles of workspace: INT8 stores of lanes outside an item
 };
 
 // Statistics pass (exponents, kappa) over both operands, then the digit

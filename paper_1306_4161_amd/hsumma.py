@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsumma.so")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_WORKSPACE = 0, -1, -2, -3, -4
-FP64, SPLIT_BF16, SPLIT_FP8 = 0, 1, 2
+FP64, SPLIT_BF16, SPLIT_FP8, SPLIT_INT8 = 0, 1, 2, 3
 DIST_BLOCK, DIST_BLOCK_CYCLIC = 0, 1
 
 EXPORTED = [

@@ -62,7 +62,7 @@ def launches(args):
     dB = torch.from_numpy(B).cuda()
     del A, B
     dC = torch.zeros((n, n), dtype=torch.float64, device="cuda")
-    prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16}[args.path]
+    prec = {"fp64": hs.FP64, "bf16": hs.SPLIT_BF16, "int8": hs.SPLIT_INT8}[args.path]
     plan = hs.Plan(n, args.P, args.Q, args.G, args.b, args.M, prec=prec)
     ws = plan.workspace()
     for g in range(min(args.count, plan.num_outer_steps)):
@@ -205,7 +205,7 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("launches")
-    a.add_argument("--path", default="fp64", choices=["fp64", "bf16"])
+    a.add_argument("--path", default="fp64", choices=["fp64", "bf16", "int8"])
     a.add_argument("--n", type=int, default=16384)
     a.add_argument("--P", type=int, default=16)
     a.add_argument("--Q", type=int, default=16)

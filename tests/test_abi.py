@@ -135,3 +135,34 @@ def test_queries_reject_bad_indices():
     with pytest.raises(hs.HsummaError):
         p.tile_shape(2, 0)
     assert p.workspace_size == 0
+
+
+def test_split_plans_validate_slices_panel_and_steps():
+    # host-only: plan validation and workspace sizing of the three digit formats
+    n, M = 512, 256
+    for prec, smax, esz in ((hs.SPLIT_BF16, 7, 2), (hs.SPLIT_FP8, 7, 1), (hs.SPLIT_INT8, 8, 1)):
+        p = hs.Plan(n, 2, 2, 1, 64, M, prec=prec)
+        lay = p.split_layout()
+        assert lay["planes"] == smax and lay["Wp"] % 32 == 0
+        # the digit planes of both operands fit in the workspace
+        assert p.workspace_size >= 2 * smax * n * lay["Wp"] * esz
+        p.close()
+        hs.Plan(n, 2, 2, 1, 64, M, prec=prec, slices=smax, min_slices=1).close()
+        with pytest.raises(hs.HsummaError) as ei:
+            hs.Plan(n, 2, 2, 1, 64, M, prec=prec, max_slices=smax + 1)
+        assert ei.value.code == hs.ERR_INVALID
+        with pytest.raises(hs.HsummaError):
+            hs.Plan(n, 2, 2, 1, 64, M, prec=prec, slices=smax + 1)
+    # exact accumulation over a panel bounds M for the FP8 and INT8 forms
+    for prec in (hs.SPLIT_FP8, hs.SPLIT_INT8):
+        hs.Plan(16384, 2, 2, 1, 64, 8192, prec=prec).close()
+        with pytest.raises(hs.HsummaError) as ei:
+            hs.Plan(16384, 2, 2, 1, 64, 16384, prec=prec)
+        assert "M <= 8192" in str(ei.value)
+    hs.Plan(16384, 2, 2, 1, 64, 16384, prec=hs.SPLIT_BF16).close()
+    # the INT8 form streams 32-k steps, the others 16-k steps
+    hs.Plan(n, 2, 2, 1, 64, M, prec=hs.SPLIT_INT8, kc=32).close()
+    hs.Plan(n, 2, 2, 1, 64, M, prec=hs.SPLIT_BF16, kc=16).close()
+    for prec, kc in ((hs.SPLIT_INT8, 16), (hs.SPLIT_BF16, 32)):
+        with pytest.raises(hs.HsummaError):
+            hs.Plan(n, 2, 2, 1, 64, M, prec=prec, kc=kc)

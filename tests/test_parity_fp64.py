@@ -204,7 +204,7 @@ def test_c3_block_cyclic_persistent_graph():
     assert np.array_equal(_run(q, dA, dB), Cn)
 
 
-@pytest.mark.parametrize("prec", [hs.FP64, hs.SPLIT_BF16])
+@pytest.mark.parametrize("prec", [hs.FP64, hs.SPLIT_BF16, hs.SPLIT_INT8])
 def test_checkpoint_resume_bitwise(prec):
     # the step boundary is a checkpoint: C after outer step s is the product
     # over the first s panels; a new plan can resume from it

@@ -1,4 +1,4 @@
-"""GPU parity of the precision form (BF16 / FP8-e4m3 digit split).
+"""GPU parity of the precision form (BF16 / FP8-e4m3 / INT8 digit split).
 
 Pins, in order of strength:
   * the matrix cores accumulate integer digit products exactly while the
@@ -8,9 +8,10 @@ Pins, in order of strength:
   * integer-valued operands that are one digit wide give the exact product;
   * every entry is within FP64 accumulation error of the oracle's exact
     value of the truncated split product (split_ref.truncated_entries);
-  * the accuracy gate: max |c_hat - c| / (|A||B|)_ij <= 1e-14 for BF16 with
-    the per-panel slice choice (c = Dot2 oracle), also reported for the plain
-    relative error.  FP8 (at most 34 bits with 7 slices) is reported, not gated.
+  * the accuracy gate: max |c_hat - c| / (|A||B|)_ij <= 1e-14 for BF16 and
+    INT8 with the per-panel slice choice (c = Dot2 oracle), also reported for
+    the plain relative error.  FP8 (at most 34 bits with 7 slices) is
+    reported, not gated.
 """
 import sys
 
@@ -77,9 +78,29 @@ def test_mfma_accumulation_exact_to_2_24(fmt, lim, k):
         assert np.abs(exact).max() <= 2 ** 24
 
 
+@pytest.mark.parametrize("k", [32, 1024])
+def test_int8_mfma_accumulation_exact_to_2_24(k):
+    import torch
+    _say("case probe int8 k=%d" % k)
+    r = np.random.default_rng(k + 7)
+    for trial in range(3):
+        if trial == 0:   # products of -128 x -128 = 2^14 add up to 2^24 at k = 1024
+            a = np.full((32, k), -128); b = np.full((k, 32), -128)
+            a[1::2] = 127
+        else:
+            a = r.integers(-128, 128, (32, k)); b = r.integers(-128, 128, (k, 32))
+        da = torch.from_numpy(a.astype(np.int8)).cuda()
+        db = torch.from_numpy(b.astype(np.int8)).cuda()
+        d = hs.mfma_exact_probe(2, da, db)
+        exact = a.astype(object) @ b.astype(object)
+        assert np.array_equal(host(d).astype(np.float64), exact.astype(np.float64)), (k, trial)
+        assert np.abs(exact).max() <= 2 ** 24
+
+
 # ------------------------------------------------------------ split stage --
 
-@pytest.mark.parametrize("prec,fmt", [(hs.SPLIT_BF16, "bf16"), (hs.SPLIT_FP8, "e4m3")])
+@pytest.mark.parametrize("prec,fmt", [(hs.SPLIT_BF16, "bf16"), (hs.SPLIT_FP8, "e4m3"),
+                                      (hs.SPLIT_INT8, "int8")])
 def test_digit_planes_match_oracle_bitwise(prec, fmt):
     import torch
     _say("case split planes %s" % fmt)
@@ -105,13 +126,18 @@ def test_digit_planes_match_oracle_bitwise(prec, fmt):
     e_ref = split_ref.exponents(A, axis=1)
     f_ref = split_ref.exponents(B, axis=0)
     assert np.array_equal(eA, e_ref) and np.array_equal(fB, f_ref)
-    DA = split_ref.digits(A, e_ref, planes, fmt, axis=1)       # (s, m, k)
-    DB = split_ref.digits(B, f_ref, planes, fmt, axis=0)       # (s, k, n)
+    # the INT8 carries depend on the count, so its digits are those of `used`
+    sd = used if fmt == "int8" else planes
+    DA = split_ref.digits(A, e_ref, sd, fmt, axis=1)           # (s, m, k)
+    DB = split_ref.digits(B, f_ref, sd, fmt, axis=0)           # (s, k, n)
     t = split_ref.FORMATS[fmt][1]
     for l in range(used):
         if fmt == "bf16":
             wa = _bf16_bits(np.ldexp(DA[l], -t * l))
             wb = _bf16_bits(np.ldexp(DB[l].T, -t * l))
+        elif fmt == "int8":
+            wa = DA[l].astype(np.int8).view(np.uint8)
+            wb = np.ascontiguousarray(DB[l].T).astype(np.int8).view(np.uint8)
         else:
             # a zero digit may come out as +0 or -0 (0x80); both are the value 0
             wa = _e4m3_bits(DA[l]); wa[wa == 0x80] = 0
@@ -123,7 +149,7 @@ def test_digit_planes_match_oracle_bitwise(prec, fmt):
 
 # -------------------------------------------------------- exact products --
 
-@pytest.mark.parametrize("prec,r", [(hs.SPLIT_BF16, 8), (hs.SPLIT_FP8, 4)])
+@pytest.mark.parametrize("prec,r", [(hs.SPLIT_BF16, 8), (hs.SPLIT_FP8, 4), (hs.SPLIT_INT8, 6)])
 def test_integer_operands_one_digit_exact(prec, r):
     _say("case integer one-digit prec=%d" % prec)
     n = 320
@@ -149,7 +175,8 @@ def test_identity_exact_for_six_digits():
 # ---------------------------------------------- truncated product parity --
 
 @pytest.mark.parametrize("prec,fmt,s", [(hs.SPLIT_BF16, "bf16", 4), (hs.SPLIT_BF16, "bf16", 6),
-                                        (hs.SPLIT_FP8, "e4m3", 5)])
+                                        (hs.SPLIT_FP8, "e4m3", 5), (hs.SPLIT_INT8, "int8", 3),
+                                        (hs.SPLIT_INT8, "int8", 8)])
 def test_equals_truncated_split_product(prec, fmt, s):
     _say("case truncated %s s=%d" % (fmt, s))
     m, k, n, M = 130, 300, 110, 128
@@ -169,15 +196,16 @@ def test_equals_truncated_split_product(prec, fmt, s):
 
 # ---------------------------------------------------------- accuracy gate --
 
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
 @pytest.mark.parametrize("dist", ["uniform", "spread2"])
-def test_bf16_auto_slices_meet_gate(dist):
-    _say("case gate %s" % dist)
+def test_auto_slices_meet_gate(dist, prec):
+    _say("case gate %s prec=%d" % (dist, prec))
     n = 1024
     if dist == "uniform":
         A = inputs.uniform(n, n, 101); B = inputs.uniform(n, n, 102)
     else:
         A = inputs.exponent_spread(n, n, 101, 2.0); B = inputs.exponent_spread(n, n, 102, 2.0)
-    p = hs.Plan(n, 4, 4, 4, 256, 256, prec=hs.SPLIT_BF16)
+    p = hs.Plan(n, 4, 4, 4, 256, 256, prec=prec)
     C, ws = _run(p, A, B)
     rows, cols = inputs.sample_entries(n, n, 4096, inputs.SEED_SAMPLE)
     c, s = core.sampled(A, B, rows, cols)
@@ -202,12 +230,13 @@ def test_fp8_reports_error_within_truncation_bound():
     _say("  fp8 s=7 max scaled err %.3g" % err.max())
 
 
-def test_c2_shape_bf16_sampled():
-    _say("case c2 split-bf16 n=16384")
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+def test_c2_shape_sampled(prec):
+    _say("case c2 split prec=%d n=16384" % prec)
     n = 16384
     A = inputs.uniform(n, n, inputs.SEED_A)
     B = inputs.uniform(n, n, inputs.SEED_B)
-    p = hs.Plan(n, 16, 16, 16, 256, 256, prec=hs.SPLIT_BF16)
+    p = hs.Plan(n, 16, 16, 16, 256, 256, prec=prec)
     C, ws = _run(p, A, B)
     edges = [i * n // 16 for i in range(16)]
     rows, cols = inputs.sample_entries(n, n, 2048, inputs.SEED_SAMPLE, edges, edges, per_edge=4)
@@ -229,15 +258,16 @@ def test_c2_shape_bf16_sampled():
     (96, 2, 96, 1, 1, 1, 2, 2),
     (96, 33, 96, 1, 1, 1, 33, 33),
 ])
-def test_degenerate_shapes_meet_gate(shape):
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+def test_degenerate_shapes_meet_gate(shape, prec):
     # exponent-spread entries on narrow panels: the per-line spread statistic
     # saturates at the panel width there, and the slice choice must still
     # meet the gate
     m, k, n, P, Q, G, b, M = shape
-    _say("case split degenerate %r" % (shape,))
+    _say("case split degenerate %r prec=%d" % (shape, prec))
     A = inputs.exponent_spread(m, k, 121, 2.0)
     B = inputs.exponent_spread(k, n, 122, 2.0)
-    p = hs.Plan(n, P, Q, G, b, M, m=m, k=k, prec=hs.SPLIT_BF16)
+    p = hs.Plan(n, P, Q, G, b, M, m=m, k=k, prec=prec)
     C, ws = _run(p, A, B)
     rows, cols = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
     rows, cols = rows.ravel(), cols.ravel()
@@ -245,17 +275,18 @@ def test_degenerate_shapes_meet_gate(shape):
     err = np.abs(C[rows, cols] - c) / np.where(s > 0, s, 1.0)
     slices = p.panel_slices(ws)
     _say("  slices %r max scaled err %.3g" % (slices, err.max()))
-    assert all(3 <= x <= 7 for x in slices)
+    assert all(3 <= x <= (8 if prec == hs.SPLIT_INT8 else 7) for x in slices)
     assert err.max() <= GATE
 
 
-def test_c3_block_cyclic_split_bf16_graph():
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+def test_c3_block_cyclic_split_graph(prec):
     import torch
-    _say("case c3 split-bf16: n=10000 6x10 block-cyclic b=128 persistent+graph")
+    _say("case c3 split prec=%d: n=10000 6x10 block-cyclic b=128 persistent+graph" % prec)
     n = 10000
     A = inputs.uniform(n, n, inputs.SEED_A)
     B = inputs.uniform(n, n, inputs.SEED_B)
-    p = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=hs.SPLIT_BF16,
+    p = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=prec,
                 persistent=1, use_graph=1)
     ws = p.workspace()
     dA, dB = dev(A), dev(B)
@@ -279,5 +310,5 @@ def test_c3_block_cyclic_split_bf16_graph():
     assert err.max() <= GATE
     check_freivalds(A, B, Cn)
     # the launch without the graph gives the same bits
-    q = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=hs.SPLIT_BF16)
+    q = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=prec)
     assert np.array_equal(_run(q, dA, dB)[0], Cn)
