@@ -950,7 +950,11 @@ __global__ __launch_bounds__(256, 1) void slice_fp8_kernel(SliceArgs p) {
 // over a whole panel (at most 8 pairs of |d d'| <= 2^14 per k, panels of at
 // most 8192 k), so each level keeps one accumulator from the item's first
 // step to its last, with no restarts, and the levels are added into FP64
-// once, scaled by 2^(-8 a), smallest weight first.
+// once, scaled by 2^(-8 a), smallest weight first.  The results go into C
+// as FP64 atomic adds issued after the next item's first steps of DMA (see
+// the epilogue), so that no wave waits for C and the next item's first
+// wait can leave the writes in flight.
+
 // Wait until at most k x PER + EXTRA of this wave's vector-memory
 // instructions are outstanding (k <= KMAX at run time; the count is an
 // immediate, capped at the counter's 63).
@@ -970,7 +974,7 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
   // DMA wave-instructions per 32-k step of waves 0-1 and 2-3
   constexpr int NIHI = 3 * (S / 2) + (S & 1 ? 2 : 0), NILO = 3 * (S / 2) + (S & 1);
   constexpr int LAG = S < 3 ? S : (S <= 5 ? 2 : 3);
-  constexpr int NSTORE = 32;                    // C stores per lane and item (2 x 16)
+  constexpr int NSTORE = 32;                    // C writes per lane and item (2 x 16)
   static_assert(NS >= 3 && NS * SB <= kBf16Lds, "LDS ring");
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform

@@ -41,6 +41,7 @@ CANDIDATES = [
                                         persistent=1)),
     ("fp64_64x64x16_persistent", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=16, persistent=1)),
     ("split_bf16", dict(prec=hs.SPLIT_BF16)),
+    ("split_int8", dict(prec=hs.SPLIT_INT8)),
 ]
 NAMES = [c[0] for c in CANDIDATES]
 DEFAULT = "fp64_128x128x16"   # what the library picks without tuning (large shapes)
@@ -64,7 +65,8 @@ class Shape:
 
 
 def allowed(shape: Shape, name: str) -> bool:
-    return not (name == "split_bf16" and shape.sigma > SPLIT_MAX_SIGMA)
+    # the split forms' FP64 accuracy is tested up to this value spread
+    return not (name.startswith("split_") and shape.sigma > SPLIT_MAX_SIGMA)
 
 
 def operands(shape: Shape, seed: int = 0):

@@ -29,7 +29,7 @@ def test_exhaustive_tune_and_cache(tmp_path):
     assert again.get(sh)["best"] == name
     spread = tune.Shape(m=512, n=512, k=512, P=1, Q=1, G=1, M=128, sigma=4.0)
     name2, _ = tune.tune(spread, tune.Cache(str(tmp_path / "c2.json")), reps=1)
-    assert name2 != "split_bf16"
+    assert not name2.startswith("split_")
 
 
 def test_learned_model_beats_default_on_held_out_shapes():
