@@ -41,8 +41,9 @@ Functions
 
 Pinned by tests/test_split_ref.py: exact reconstruction with enough digits,
 the remainder bound, digit range and integrality, exactness of the digits in
-torch bfloat16 / float8_e4m3fn, integer-valued inputs as single digits, and
-brute-force exact products.  The choice of rule itself is a reading (the
+torch bfloat16 / float8_e4m3fn / int8, INT8 carries worked by hand (a tie, a
+negative tie, a two-step cascade, and the count dependence), integer-valued
+inputs as single digits, and brute-force exact products.  The choice of rule itself is a reading (the
 paper has no precision form); parity of the split GPU path against this
 reference is to the truncation bound plus FP64 accumulation error.
 """
