@@ -194,6 +194,30 @@ def test_equals_truncated_split_product(prec, fmt, s):
     assert np.all(np.abs(C[rows, cols] - T) <= tol)
 
 
+@pytest.mark.parametrize("prec,fmt,s", [(hs.SPLIT_INT8, "int8", 8), (hs.SPLIT_BF16, "bf16", 7)])
+def test_truncated_product_with_many_items_per_workgroup(prec, fmt, s):
+    # 2000 x 1900 with 64 x 128 macro-tiles is 32 x 15 = 480 items, so most
+    # persistent workgroups run two (or more) items back to back: the INT8
+    # kernel then issues an item's first DMA steps during the previous
+    # item's epilogue and leaves that item's C writes in flight across its
+    # first wait.  Ragged last rows and columns, two panels.
+    _say("case truncated many items %s s=%d" % (fmt, s))
+    m, k, n, M = 2000, 512, 1900, 256
+    A = inputs.exponent_spread(m, k, 131, sigma=2.0)
+    B = inputs.exponent_spread(k, n, 132, sigma=2.0)
+    p = hs.Plan(n, 2, 2, 4, 64, M, m=m, k=k, prec=prec, slices=s, min_slices=1)
+    assert p.num_items > 256
+    C, _ = _run(p, A, B)
+    r = np.random.default_rng(5)
+    rows = np.concatenate([r.integers(0, m, 300), np.arange(m - 8, m), np.arange(8)])
+    cols = np.concatenate([r.integers(0, n, 300), np.arange(n - 8, n), np.arange(8)])
+    T = split_ref.truncated_entries(A, B, M, s, fmt, rows, cols)
+    S = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    nadd = 8 * (k // 32 + 2) + 4 * (k // M + 1)
+    tol = nadd * core.U * (S + np.abs(T))
+    assert np.all(np.abs(C[rows, cols] - T) <= tol)
+
+
 # ---------------------------------------------------------- accuracy gate --
 
 @pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
