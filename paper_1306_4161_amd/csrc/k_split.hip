@@ -480,6 +480,18 @@ __device__ __forceinline__ void vm_wait_steps(int k) {
   else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Wait until at most k x PER + EXTRA of this wave's vector-memory
+// instructions are outstanding (k <= KMAX at run time; the count is an
+// immediate, capped at the counter's 63).
+template <int PER, int KMAX, int EXTRA>
+__device__ __forceinline__ void vm_wait_steps_plus(int k) {
+  if (KMAX >= 4 && k >= 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 4 * PER + EXTRA)) : "memory");
+  else if (KMAX >= 3 && k == 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 3 * PER + EXTRA)) : "memory");
+  else if (KMAX >= 2 && k == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 2 * PER + EXTRA)) : "memory");
+  else if (KMAX >= 1 && k == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, PER + EXTRA)) : "memory");
+  else asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, EXTRA)) : "memory");
+}
+
 template <int S>
 __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* smem) {
   constexpr int TM = kBf16TM, TN = kBf16TN, NW = kBf16NW, NS = bf16_stages(S);
@@ -491,11 +503,19 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
   constexpr int LAG = S < 3 ? S : (S <= 5 ? 2 : 3);
   static_assert(NS >= 3 && NS * SB <= kBf16Lds, "LDS ring");
 
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+  constexpr int NSTORE = 32;                    // C writes per lane and item (2 x 16)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
   const int wm = wave >> 1, wn = wave & 1;
-  const int l32 = lane & 31, lh = lane >> 5;
   const bool hi = wave < 2;                     // this wave issues NIHI per step
+  // Per-lane offsets come from a lane id read where they are needed, opaque
+  // to the compiler (v_mbcnt): derived once, they would stay live across
+  // the epilogue and be spilled, and a scratch reload after the next item's
+  // DMA would wait for that DMA and the epilogue's writes.
+  auto lane_id = [] {
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+  };
 
   const __amdgpu_buffer_rsrc_t rsrcA =
       __builtin_amdgcn_make_buffer_rsrc((void*)p.digA, (short)0, (int)p.bytesA, kBufferWord3);
@@ -504,20 +524,24 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
   const uint32_t kbA = (uint32_t)p.rowsA * 32u, kbB = (uint32_t)p.rowsB * 32u;  // bytes per k16 block
   const uint32_t planeAB = (uint32_t)(p.planeA * 2), planeBB = (uint32_t)(p.planeB * 2);
   const int nsteps = p.Wp / 16;                // a multiple of 4
-  const int arow = wm * 32 + l32;
-  const int aoff = (arow * 2 + (lh ^ ((arow >> 3) & 1))) * 16;
-  const int bcol = wn * 64 + l32;              // block 1 is 32 columns on: same swizzle bit
-  const int boff = (bcol * 2 + (lh ^ ((bcol >> 3) & 1))) * 16;
+  // LDS byte offsets of this lane's A and B fragments (block 1 is 32
+  // columns on: same swizzle bit)
+  auto frag_offsets = [&](int& aoff, int& boff) {
+    const int l = lane_id(), l32 = l & 31, lh = l >> 5;
+    const int arow = wm * 32 + l32, bcol = wn * 64 + l32;
+    aoff = (arow * 2 + (lh ^ ((arow >> 3) & 1))) * 16;
+    boff = (bcol * 2 + (lh ^ ((bcol >> 3) & 1))) * 16;
+  };
 
   const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
   const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;
-
-  for (int slot = slot0;; slot += slots) {
-    if (!p.persistent && slot != slot0) break;
-    if (slot >= p.per_xcd) break;
+  // the work item of a slot of this workgroup, or -1
+  auto item_index = [&](int slot) {
+    if (!p.persistent && slot != slot0) return -1;
+    if (slot >= p.per_xcd) return -1;
     const int idx = xcd * p.per_xcd + slot;
-    if (idx >= p.nitems) break;
-    const WorkItem it = p.items[idx];
+    return idx < p.nitems ? idx : -1;
+  };
 
     // DMA: a 16-k step moves, per plane, 2 wave-instructions of A (64 rows x
     // 32 bytes) and 4 of B (128 columns x 32 bytes), 64 16-byte units each
@@ -527,14 +551,16 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
     // wave has one per-lane byte offset into A and one into B (ragged rows
     // and columns clamped to the last valid one); plane and k16 block are a
     // uniform offset in the buffer descriptor's soffset.
-    const int ua = (wave & 1) * 64 + lane;
+  uint32_t voffA = 0, voffB = 0;
+  auto set_dma_offsets = [&](const WorkItem& w) {
+    const int l = lane_id();
+    const int ua = (wave & 1) * 64 + l;
     const int rowa = ua >> 1, halfa = (ua & 1) ^ ((rowa >> 3) & 1);
-    const uint32_t voffA = (uint32_t)(it.r0 + min(rowa, it.h - 1)) * 32u + halfa * 16u;
-    const int ub = wave * 64 + lane;
+    const int ub = wave * 64 + l;
     const int colb = ub >> 1, halfb = (ub & 1) ^ ((colb >> 3) & 1);
-    const uint32_t voffB = (uint32_t)(it.c0 + min(colb, it.w - 1)) * 32u + halfb * 16u;
-    // row of this lane's D item v in the item
-    auto erow = [&](int v) { return wm * 32 + 8 * (v >> 2) + 4 * lh + (v & 3); };
+    voffA = (uint32_t)(w.r0 + min(rowa, w.h - 1)) * 32u + halfa * 16u;
+    voffB = (uint32_t)(w.c0 + min(colb, w.w - 1)) * 32u + halfb * 16u;
+  };
     auto dmaA = [&](int plane, int kb, uint8_t* dst) {
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           rsrcA, (__attribute__((address_space(3))) void*)dst, 16, voffA,
@@ -565,6 +591,37 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
       else vm_wait_steps<NILO, NS - 1>(later);
     };
 
+  int idx = item_index(slot0);
+  if (idx < 0) return;
+  WorkItem it = p.items[idx];
+  set_dma_offsets(it);
+
+  // Fragments.  Rows run in the order r = 0 .. S-1, row r pairing A
+  // fragment S-1-r with B fragments 0 .. r, so each row needs one new A and
+  // one new B fragment (per block).  Reads run LAG rows ahead of the MFMAs;
+  // the last LAG rows of a step read the first LAG rows of the next step
+  // (or item) into the other register set.
+  bf8v fa[2][S], fb0[2][S], fb1[2][S];
+  int aoff, boff;
+  auto read_row = [&](int set, int st, int r) {
+    const uint8_t* sA = smem + st * SB;
+    const uint8_t* sB = sA + ABYTES;
+    fa[set][S - 1 - r] = *(const bf8v*)(sA + (S - 1 - r) * (TM * 32) + aoff);
+    fb0[set][r] = *(const bf8v*)(sB + r * (TN * 32) + boff);
+    fb1[set][r] = *(const bf8v*)(sB + r * (TN * 32) + boff + 1024);
+  };
+  // the first item's prologue: NS steps in flight, step 0 landed, the first
+  // LAG rows of fragments read
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+    if (st < nsteps) issue(st, st);
+  wait_step(min(NS - 1, nsteps - 1));
+  ring_barrier();
+  frag_offsets(aoff, boff);
+#pragma unroll
+  for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
+
+  for (int slot = slot0; idx >= 0; slot += slots) {
     f16v acc0[NACC], acc1[NACC];               // level accumulators, blocks 0 and 1
     double cp0[16], cp1[16];                   // FP64 panel sums
 #pragma unroll
@@ -572,20 +629,6 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
       cp0[v] = 0.0;
       cp1[v] = 0.0;
     }
-
-    // Fragments.  Rows run in the order r = 0 .. S-1, row r pairing A
-    // fragment S-1-r with B fragments 0 .. r, so each row needs one new A and
-    // one new B fragment (per block).  Reads run LAG rows ahead of the MFMAs;
-    // the last LAG rows of a step read the first LAG rows of the next step
-    // into the other register set.
-    bf8v fa[2][S], fb0[2][S], fb1[2][S];
-    auto read_row = [&](int set, int st, int r) {
-      const uint8_t* sA = smem + st * SB;
-      const uint8_t* sB = sA + ABYTES;
-      fa[set][S - 1 - r] = *(const bf8v*)(sA + (S - 1 - r) * (TM * 32) + aoff);
-      fb0[set][r] = *(const bf8v*)(sB + r * (TN * 32) + boff);
-      fb1[set][r] = *(const bf8v*)(sB + r * (TN * 32) + boff + 1024);
-    };
     // In the first step of a group of four every accumulator starts from
     // zero: its first pair (row S-1-a, or row 0 for the shared deep one, with
     // l2 = 0) takes a zero C operand.
@@ -655,15 +698,6 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
       return m;
     };
 
-    // prologue: NS steps in flight, then the first LAG rows of step 0
-#pragma unroll
-    for (int st = 0; st < NS; ++st)
-      if (st < nsteps) issue(st, st);
-    wait_step(min(NS - 1, nsteps - 1));
-    ring_barrier();
-#pragma unroll
-    for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
-
     int ci = 0;
     for (; ci + 8 <= nsteps; ci += 8) {
       static_for<0, 8>([&](auto jc) {
@@ -680,33 +714,67 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
       step(ci + 3, 1, 0);
       flush(ALL);
     }
-    __syncthreads();  // the ring is reused by the next item
 
-    // C += 2^(e_i + f_j - 16) x panel sum.  Addresses are clamped into the
-    // item so that every load is unconditional (all in flight at once); only
-    // the stores are predicated.
-    // exponents of the lane's 16 rows (clamped into the item)
-    int ea[16];
+    // Epilogue (as in the INT8 kernel): (1) the exponent loads; (2) once they
+    // have landed and every wave is done with the ring, the next item's first
+    // NS steps of DMA; (3) C += 2^(e_i + f_j - 16) x panel sum as FP64
+    // atomic adds (the first panel of a product stores instead): no wave
+    // waits for C, each C element gets exactly one add per launch, so the
+    // result is the single rounded sum a load and a store would give, and
+    // the next item's first wait leaves these NSTORE writes in flight.
+    const int lane_e = lane_id();
+    const int le32 = lane_e & 31, leh = lane_e >> 5;
+    auto erow = [&](int v) { return wm * 32 + 8 * (v >> 2) + 4 * leh + (v & 3); };
+    int ea[16], fq[2];
 #pragma unroll
     for (int v = 0; v < 16; ++v) ea[v] = p.eA[it.r0 + min(erow(v), it.h - 1)];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {         // one 32-column block at a time
-      const int col = wn * 64 + q * 32 + l32;
-      const int fq = p.fB[it.c0 + min(col, it.w - 1)];
-      double cold[16];
-      if (!p.zero_init) {
+    for (int q = 0; q < 2; ++q) fq[q] = p.fB[it.c0 + min(wn * 64 + q * 32 + le32, it.w - 1)];
+    // the exponents have landed before the DMA is issued (vmcnt(0), an
+    // S_WAITCNT the compiler sees), so that no wait for them after it can
+    // hold the DMA too
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_sched_barrier(0);
+    // every wave's reads of the ring have retired, and no DMA of this item is
+    // outstanding
+    ring_barrier();
+    const int nidx = __builtin_amdgcn_readfirstlane(item_index(slot + slots));
+    WorkItem nt = it;
+    if (nidx >= 0) {
+      nt = p.items[nidx];
+      set_dma_offsets(nt);
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          cold[v] = p.C[(int64_t)(it.r0 + min(erow(v), it.h - 1)) * p.ldc + it.c0 +
-                        min(col, it.w - 1)];
-      }
+      for (int st = 0; st < NS; ++st)
+        if (st < nsteps) issue(st, st);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // Every lane issues all NSTORE writes: lanes outside a ragged item write
+    // to their own slot of the dump area, so that the count the next item's
+    // first wait allows for is exact.
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int col = wn * 64 + q * 32 + le32;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = erow(v);
-        const double add = ldexp(q ? cp1[v] : cp0[v], ea[v] + fq - 16);
-        if (row < it.h && col < it.w)
-          p.C[(int64_t)(it.r0 + row) * p.ldc + it.c0 + col] = p.zero_init ? add : cold[v] + add;
+        const double add = ldexp(q ? cp1[v] : cp0[v], ea[v] + fq[q] - 16);
+        const bool in = row < it.h && col < it.w;
+        double* dst = in ? p.C + (int64_t)(it.r0 + row) * p.ldc + it.c0 + col : p.dump + lane_e;
+        if (p.zero_init) *dst = add;
+        else unsafeAtomicAdd(dst, add);
       }
+    }
+    it = nt;
+    idx = nidx;
+    if (idx >= 0) {
+      // the next item's step 0 landed; its writes above are the newest
+      // NSTORE vector-memory instructions and need not have completed
+      if (hi) vm_wait_steps_plus<NIHI, NS - 1, NSTORE>(min(NS - 1, nsteps - 1));
+      else vm_wait_steps_plus<NILO, NS - 1, NSTORE>(min(NS - 1, nsteps - 1));
+      ring_barrier();
+      frag_offsets(aoff, boff);
+#pragma unroll
+      for (int r = 0; r < LAG; ++r) read_row(0, 0, r);
     }
   }
 }
@@ -954,18 +1022,6 @@ __global__ __launch_bounds__(256, 1) void slice_fp8_kernel(SliceArgs p) {
 // as FP64 atomic adds issued after the next item's first steps of DMA (see
 // the epilogue), so that no wave waits for C and the next item's first
 // wait can leave the writes in flight.
-
-// Wait until at most k x PER + EXTRA of this wave's vector-memory
-// instructions are outstanding (k <= KMAX at run time; the count is an
-// immediate, capped at the counter's 63).
-template <int PER, int KMAX, int EXTRA>
-__device__ __forceinline__ void vm_wait_steps_plus(int k) {
-  if (KMAX >= 4 && k >= 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 4 * PER + EXTRA)) : "memory");
-  else if (KMAX >= 3 && k == 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 3 * PER + EXTRA)) : "memory");
-  else if (KMAX >= 2 && k == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, 2 * PER + EXTRA)) : "memory");
-  else if (KMAX >= 1 && k == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, PER + EXTRA)) : "memory");
-  else asm volatile("s_waitcnt vmcnt(%0)" ::"n"(min(63, EXTRA)) : "memory");
-}
 
 template <int S>
 __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem) {
