@@ -218,6 +218,32 @@ def test_truncated_product_with_many_items_per_workgroup(prec, fmt, s):
     assert np.all(np.abs(C[rows, cols] - T) <= tol)
 
 
+@pytest.mark.parametrize("prec,fmt,s", [(hs.SPLIT_INT8, "int8", 6), (hs.SPLIT_BF16, "bf16", 5)])
+def test_local_updates_are_truncated_products_of_inner_panels(prec, fmt, s):
+    # hsumma_local_update splits the k-range of its inner step on its own, so
+    # the sum of every step's update is the truncated split product with
+    # panels of width b (here with a fixed slice count)
+    import torch
+    _say("case local updates %s s=%d" % (fmt, s))
+    m, k, n, b, M = 200, 384, 170, 64, 128
+    A = inputs.exponent_spread(m, k, 141, sigma=2.0)
+    B = inputs.exponent_spread(k, n, 142, sigma=2.0)
+    p = hs.Plan(n, 2, 2, 2, b, M, m=m, k=k, prec=prec, slices=s, min_slices=1)
+    ws = p.workspace()
+    dA, dB = dev(A), dev(B)
+    C = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+    for st in range(p.num_steps):
+        p.local_update(st, dA, dB, C, ws=ws)
+    C = host(C)
+    rows, cols = np.meshgrid(np.arange(0, m, 3), np.arange(0, n, 2), indexing="ij")
+    rows, cols = rows.ravel(), cols.ravel()
+    T = split_ref.truncated_entries(A, B, b, s, fmt, rows, cols)
+    S = (np.abs(A) @ np.abs(B))[rows, cols]
+    nadd = 8 * (k // 32 + 2) + 4 * (k // b + 1)
+    tol = nadd * core.U * (S + np.abs(T))
+    assert np.all(np.abs(C[rows, cols] - T) <= tol)
+
+
 # ---------------------------------------------------------- accuracy gate --
 
 @pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
