@@ -1029,7 +1029,9 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
   constexpr int ABYTES = S * TM * 32, BBYTES = S * TN * 32, SB = ABYTES + BBYTES;
   // DMA wave-instructions per 32-k step of waves 0-1 and 2-3
   constexpr int NIHI = 3 * (S / 2) + (S & 1 ? 2 : 0), NILO = 3 * (S / 2) + (S & 1);
-  constexpr int LAG = S < 3 ? S : (S <= 5 ? 2 : 3);
+  // rows of fragment reads ahead of the MFMAs: 2 (at s = 8, 1.5 % faster than 3;
+  // even at s = 6)
+  constexpr int LAG = S < 3 ? S : 2;
   constexpr int NSTORE = 32;                    // C writes per lane and item (2 x 16)
   static_assert(NS >= 3 && NS * SB <= kBf16Lds, "LDS ring");
 
