@@ -5,7 +5,7 @@ problem shape (sizes, grid, groups, outer block, value spread).  Output: the
 predicted log2 run time of every candidate configuration; the prediction
 picks the allowed candidate with the smallest one, so a new shape needs one
 forward pass instead of an exhaustive search.  Exhaustive search stays the
-fallback and the judge: regret = t(picked) / t(best) - 1.
+fallback and the yardstick: regret = t(picked) / t(best) - 1.
 
 Training and inference run in the library's own HIP kernels
 (hsumma_mlp_grad / hsumma_mlp_adam / hsumma_mlp_forward); this module only
