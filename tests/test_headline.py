@@ -1,0 +1,118 @@
+"""GPU parity at the benchmarked workload: n = 16384, 16 x 16 grid, G = 16
+(4 x 4 groups of 4 x 4 processors), inner block b = 256, outer block M = 1024,
+entries u * 2^rint(N(0, 4)), u ~ U[-1, 1] (seeds A = 2013, B = 4161).
+
+Every path the benchmark can report as FP64-accurate is asserted here, on the
+same operands and launch configuration the benchmark times:
+
+  * FP64 MFMA: each sampled entry within gamma_K (|A||B|)_ij of the Dot2
+    oracle (the classic bound of any FP64 dot product, Higham Sec. 3.1), and
+    also at M = b = 256 (the outer block equal to the inner one, the paper's
+    b = B runs, Sec. V);
+  * the BF16 and INT8 digit splits with the per-panel slice choice: max
+    |c_hat - c| / (|A||B|)_ij <= 1e-14 on the same samples;
+  * Freivalds' check with three random sign vectors for every path (a
+    dropped or repeated panel or a misplaced tile fails it).
+
+Samples: 2048 uniform entries plus 32 on the first and last row and column of
+every 1024 x 1024 processor tile (4096 in all), seed 1306.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_1306_4161_amd import hsumma as hs
+from paper_1306_4161_amd import inputs
+
+from gpu_helpers import check_sampled, host
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-14
+N, P, Q, G, B_IN, M_OUT, SIGMA = 16384, 16, 16, 16, 256, 1024, 2.0
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def workload():
+    import torch
+    _say("headline workload: generating n=%d sigma=%g operands" % (N, SIGMA))
+    A = inputs.exponent_spread(N, N, inputs.SEED_A, SIGMA)
+    B = inputs.exponent_spread(N, N, inputs.SEED_B, SIGMA)
+    edges = [i * N // P for i in range(P)]
+    rows, cols = inputs.sample_entries(N, N, 2048, inputs.SEED_SAMPLE, edges, edges, per_edge=32)
+    assert rows.size == 4096
+    c, s = core.sampled(A, B, rows, cols)
+    _say("headline workload: Freivalds references")
+    fre = []
+    absA = np.abs(A)
+    for sd in (1, 2, 3):
+        x = inputs.rademacher(N, sd)
+        y, sy = core.matvec2(B, x)
+        z, _ = core.matvec2(A, y)
+        _, sz = core.matvec2(absA, sy)
+        fre.append((x, z, sz))
+    del absA
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    return dict(A=A, B=B, dA=dA, dB=dB, rows=rows, cols=cols, c=c, s=s, fre=fre)
+
+
+def _run(w, prec, M):
+    import torch
+    plan = hs.Plan(N, P, Q, G, B_IN, M, prec=prec)
+    assert plan.groups == (4, 4)
+    assert plan.num_steps == N // B_IN and plan.num_outer_steps == N // M
+    ws = plan.workspace()
+    C = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    C.fill_(float("nan"))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.run(w["dA"], w["dB"], C, ws=ws, stream=stream)
+    stream.synchronize()
+    slices = plan.panel_slices(ws) if prec != hs.FP64 else None
+    return host(C), slices
+
+
+def _freivalds(w, Ch):
+    K = N
+    for x, z, sz in w["fre"]:
+        v, sv = core.matvec2(Ch, x)
+        resid = np.abs(v - z)
+        bound = (core.gamma(K) + 4 * core.U) * sz + 2 * core.U * sv
+        assert np.all(resid <= bound), "Freivalds: max ratio %g" % float(
+            np.max(resid / np.maximum(bound, 1e-300)))
+
+
+def _scaled(w, Ch):
+    got = Ch[w["rows"], w["cols"]]
+    return float(np.max(np.abs(got - w["c"]) / w["s"]))
+
+
+@pytest.mark.parametrize("M", [M_OUT, B_IN])
+def test_headline_fp64(workload, M):
+    _say("case headline fp64 n=%d M=%d" % (N, M))
+    Ch, _ = _run(workload, hs.FP64, M)
+    sc = check_sampled(workload["A"], workload["B"], Ch, workload["rows"], workload["cols"])
+    _say("  fp64 M=%d max scaled err %.3g" % (M, sc))
+    assert sc <= GATE
+    _freivalds(workload, Ch)
+
+
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+def test_headline_split_meets_gate(workload, prec):
+    _say("case headline split prec=%d n=%d M=%d" % (prec, N, M_OUT))
+    Ch, slices = _run(workload, prec, M_OUT)
+    sc = _scaled(workload, Ch)
+    _say("  slices %r max scaled err %.3g" % (sorted(set(slices)), sc))
+    assert len(slices) == N // M_OUT
+    assert np.all(np.isfinite(Ch[workload["rows"], workload["cols"]]))
+    assert sc <= GATE
+    _freivalds(workload, Ch)
