@@ -224,7 +224,7 @@ def main():
             # time the product kernel alone on the last split panel
             C2 = torch.empty_like(dC)
             last = nouter - 1
-            prod = lambda: plan.outer_products(last, C2, ws, stream=stream)
+            prod = lambda: plan.outer_products(last, pA, pB, C2, ws, stream=stream)
             with torch.cuda.stream(stream):
                 prod()
             torch.cuda.synchronize()

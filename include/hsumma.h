@@ -23,15 +23,28 @@
  * it is the set of distribution blocks the processor owns.  Column-major
  * callers pass transposed problems.
  *
- * Ownership.  The caller owns A, B, C and the workspace `ws` (device memory
- * of at least hsumma_workspace_size() bytes; may be NULL when that size is
- * 0).  A plan is a host object; on first use on a device it uploads its
- * work-item table to device memory it allocates and frees in
- * hsumma_plan_destroy().  Captured HIP graphs are owned by the plan.
+ * Ownership.  The caller owns A, B, C and the workspace `ws`: device memory
+ * of at least hsumma_workspace_size() bytes, 256-byte aligned, required by
+ * every compute call of every precision.  The library allocates no device
+ * memory and copies nothing from the host to the device: each compute call
+ * first writes the plan's work-item table (the macro-tiles of every virtual
+ * processor, see hsumma_work_items) into `ws` with a small kernel, then
+ * launches the update kernels, which read their operands and the workspace
+ * only.  A plan is a host object; a HIP graph it captures (opts.use_graph)
+ * is owned by the plan and released by hsumma_plan_destroy().  A, B, C and
+ * `ws` must be ordinary (coarse-grained) device memory of the current
+ * device: the split forms add into C with FP64 atomic adds, which need it.
  *
  * Streams and synchronisation.  `stream` is a hipStream_t passed as void*
  * (NULL = the null stream).  All compute calls are asynchronous on it and
- * never synchronise the device.  A, B and C must not alias.
+ * never synchronise the device or the host; only hsumma_panel_slices waits
+ * for `stream`.  A, B, C and ws must not overlap.  Calls that share a
+ * workspace must be ordered (one stream, or events).
+ *
+ * Non-finite inputs.  The FP64 path follows IEEE arithmetic (an Inf or NaN
+ * in A or B reaches the entries of C whose sums include it).  The split
+ * forms detect Inf and NaN in a panel and compute that panel with the FP64
+ * kernel instead, so they propagate the same way.
  *
  * Errors.  Every int-returning call returns an hsumma_status.  Invalid
  * arguments return HSUMMA_ERR_INVALID (nothing is launched); HIP failures
@@ -88,8 +101,11 @@ typedef struct {
   int32_t tau_bits;   /* split forms, per-panel slice choice: the smallest s    */
                       /* whose modelled max error relative to (|A||B|)_ij is    */
                       /* <= 2^-tau_bits (model: bits(s) against the panel's     */
-                      /* value spread and k; max_slices when the spread         */
-                      /* statistic is saturated by a narrow panel);             */
+                      /* value spread and k, with random-sign cancellation over */
+                      /* k credited only when no line repeats its low-order     */
+                      /* bits; max_slices when the spread statistic is          */
+                      /* saturated by a narrow panel); a panel needing more     */
+                      /* than max_slices goes to the FP64 kernel;               */
                       /* 0 => 48 (50 for INT8)                                  */
   int32_t staged;     /* FP64 path: 1 = always the register-staged kernel,      */
                       /* 0 = direct-to-LDS loads where alignment allows         */
@@ -113,11 +129,17 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G,
 void hsumma_plan_destroy(hsumma_plan_t plan);
 
 /* Queries (host only). */
+/* Bytes of device workspace every compute call needs (> 0). */
 int hsumma_workspace_size(hsumma_plan_t plan, size_t* bytes);
-int hsumma_num_steps(hsumma_plan_t plan, int64_t* steps);          /* inner steps: sum over outer
-                                                                      blocks of ceil(width/b) */
-int hsumma_num_outer_steps(hsumma_plan_t plan, int64_t* steps);    /* ceil(k/M) */
-int hsumma_groups(hsumma_plan_t plan, int32_t* I, int32_t* J);
+/* Inner steps (Sec. III: k/b steps of width b, the k/M outer blocks each
+ * split into M/b): the sum over outer blocks of ceil(width/b), so a ragged
+ * last block of k gives a shorter last step. */
+int hsumma_num_steps(hsumma_plan_t plan, int64_t* steps);
+int hsumma_num_outer_steps(hsumma_plan_t plan, int64_t* steps);    /* ceil(k/M), Sec. III */
+int hsumma_groups(hsumma_plan_t plan, int32_t* I, int32_t* J);     /* Sec. III arrangement */
+/* Rows and columns of C owned by processor (pr, pc) (Sec. II-A: processor
+ * (i, j) owns one block of C; the block-cyclic distribution of Sec. VI owns
+ * every P-th (Q-th) block of nb rows (columns) starting at pr (pc)). */
 int hsumma_tile_shape(hsumma_plan_t plan, int32_t pr, int32_t pc,
                       int64_t* m_loc, int64_t* n_loc);
 /*
@@ -132,6 +154,23 @@ int hsumma_step_info(hsumma_plan_t plan, int64_t s, int64_t* k0, int64_t* k1,
                      int32_t* in_group_col, int32_t* in_group_row);
 /* Number of work items (macro-tiles over all tiles) per launch. */
 int hsumma_num_items(hsumma_plan_t plan, int64_t* items);
+/*
+ * The work-item table the compute calls write into the workspace, as the
+ * plan defines it (host memory, out has 4 x hsumma_num_items() int32):
+ * item t is rows [r0, r0 + h) and columns [c0, c0 + w) of C, stored as
+ * out[4t .. 4t+3] = r0, c0, h, w.  Items are listed group by group (Sec.
+ * III), processor by processor inside a group and macro-tile by macro-tile
+ * inside a processor's tile (Sec. II-A), cut into 8 equal consecutive
+ * lists (one per XCD); in the persistent mode and the split forms each list
+ * is in decreasing order of area (stable).
+ */
+int hsumma_work_items(hsumma_plan_t plan, int32_t* out, int64_t capacity);
+/*
+ * Write the work-item table into the workspace (bytes [0, 16 x items) of
+ * ws, the layout of hsumma_work_items), as every compute call does first.
+ * Asynchronous on `stream`.
+ */
+int hsumma_prepare_workspace(hsumma_plan_t plan, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * One inner step s (0 <= s < num_steps): for every tile,
@@ -143,9 +182,13 @@ int hsumma_local_update(hsumma_plan_t plan, int64_t step,
                         double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * One outer step g: all inner steps of the outer block in one launch, C held
- * in registers across them.  Bitwise equal to the sequence of its
- * hsumma_local_update calls.  Accumulates into C.
+ * One outer step g (Sec. III: the between-group step of width M): all inner
+ * steps of the outer block in one launch, C held in registers across them.
+ * Accumulates into C.  FP64 path: bitwise equal to the sequence of its
+ * hsumma_local_update calls (the MFMA k-groups restart at every inner-step
+ * boundary).  Split forms: the outer step splits its M-wide panel once,
+ * while each hsumma_local_update splits its own b-wide panel, so the two
+ * truncate differently (each is the truncated product of its own panels).
  */
 int hsumma_outer_update(hsumma_plan_t plan, int64_t outer,
                         const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -154,24 +197,31 @@ int hsumma_outer_update(hsumma_plan_t plan, int64_t outer,
 /*
  * Split forms only: the slice-product launch of outer step g alone, on the
  * digit planes the workspace holds from a previous call that split that
- * outer step's panel (C += its product).  Lets a caller time or repeat the
- * matrix-core part without the split.
+ * outer step's panel (C += its product); a panel that split sent to the
+ * FP64 kernel (slice count 0) is recomputed by it from A and B.  Lets a
+ * caller time or repeat the matrix-core part without the split.
  */
-int hsumma_outer_products(hsumma_plan_t plan, int64_t outer, double* C, int64_t ldc, void* ws,
+int hsumma_outer_products(hsumma_plan_t plan, int64_t outer, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, double* C, int64_t ldc, void* ws,
                           size_t ws_bytes, void* stream);
 
 /*
- * The whole product C = A x B: every outer step in order (the first one
- * stores instead of accumulating, so C needs no clearing).  With
- * opts.use_graph the launch sequence is captured once per (pointers, stream)
- * and replayed.
+ * The whole product C = A x B (Alg. 1: every outer step of width M, each of
+ * M/b inner steps; Sec. II-A: c_ij = sum_k a_ik b_kj once all steps are
+ * done): every outer step in order, the first one storing instead of
+ * accumulating, so C needs no clearing.  With
+ * opts.use_graph the launch sequence (work-item table included) is captured
+ * once per (pointers, stream, device) and replayed.
  */
 int hsumma_run(hsumma_plan_t plan, const double* A, int64_t lda, const double* B,
                int64_t ldb, double* C, int64_t ldc, void* ws, size_t ws_bytes,
                void* stream);
 
 /* Slice count chosen for each outer panel by the last split-form call
- * (copied to host; synchronises `stream`).  counts has num_outer_steps room. */
+ * (copied to host; synchronises `stream`).  counts has num_outer_steps room.
+ * A count of 0 means the panel was computed by the FP64 kernel: it held an
+ * Inf or a NaN, or (automatic count) the slice-count model needed more than
+ * max_slices digits for an error within 2^-tau_bits of (|A||B|)_ij. */
 int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, void* stream);
 
 /*

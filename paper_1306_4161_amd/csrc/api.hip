@@ -7,11 +7,15 @@
 // items are ordered group by group and tile by tile, and that list is cut
 // into 8 contiguous parts, one per XCD: the processors of a group share an
 // L2, the GPU's image of the paper's group-level broadcast.
+//
+// Device memory: the library allocates none.  Every compute call writes the
+// plan's work-item table into the caller's workspace with one small kernel
+// (k_items.hip) before its update launches, so a call depends on nothing but
+// its arguments, and a captured graph regenerates the table on each replay.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <map>
 #include <mutex>
 #include <new>
 
@@ -54,10 +58,6 @@ struct StepRec {
   int64_t k0, k1, outer;
 };
 
-struct DeviceState {
-  hs::WorkItem* items = nullptr;
-};
-
 struct GraphKey {
   const void* A; int64_t lda; const void* B; int64_t ldb; void* C; int64_t ldc;
   void* ws; void* stream;
@@ -79,13 +79,16 @@ struct hsumma_plan_s {
   std::vector<int64_t> outer_lo;              // k start of each outer step (+ end)
   std::vector<hs::WorkItem> items;
   int32_t per_xcd = 0;
+  int32_t br = 1, bc = 1;      // macro-tiles per block inside a processor's tile
+  bool lpt = false;            // XCD lists in longest-first order
   bool items_even = false;     // every work item starts at an even column, has even width
-  // precision form: workspace layout (byte offsets) and panel geometry
+  // workspace layout (byte offsets): the work-item table (every precision),
+  // then the precision form's digit planes, exponents and statistics
+  size_t off_items = 0, off_items_tmp = 0, off_prefix = 0;
   int32_t fmt = -1;            // -1: FP64 path; 0: BF16, 1: FP8-e4m3, 2: INT8 digits
   int32_t Wp = 0;              // padded panel width
   size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_stats = 0, off_slices = 0,
          off_dump = 0, ws_bytes = 0;
-  std::map<int, DeviceState> dev;
   std::mutex mu;
   bool have_graph = false;
   GraphKey gkey{};
@@ -160,8 +163,10 @@ void build_items(hsumma_plan_s& p) {
   // of C: they then share the fewest A rows plus B columns per k-slice in
   // that XCD's L2.
   const int conc = 32 * (p.fmt < 0 ? std::max(1, hs::fp64_occupancy(p.cfg)) : 1);
-  int bc = std::max(1, (int)std::lround(std::sqrt((double)conc * p.cfg.tm / p.cfg.tn)));
-  int br = std::max(1, conc / bc);
+  const int bc = std::max(1, (int)std::lround(std::sqrt((double)conc * p.cfg.tm / p.cfg.tn)));
+  const int br = std::max(1, conc / bc);
+  p.br = br;
+  p.bc = bc;
   p.items.clear();
   for (int x = 0; x < p.I; ++x)
     for (int y = 0; y < p.J; ++y)
@@ -184,7 +189,8 @@ void build_items(hsumma_plan_s& p) {
   p.items_even = true;
   for (auto& it : p.items)
     if ((it.c0 | it.w) & 1) p.items_even = false;
-  if (p.opts.persistent || p.fmt >= 0) {
+  p.lpt = p.opts.persistent || p.fmt >= 0;
+  if (p.lpt) {
     // Longest-processing-time order inside each XCD's list, so that the
     // static round-robin of the persistent workgroups stays balanced when
     // tiles are uneven (ragged block-cyclic edges).
@@ -198,29 +204,33 @@ void build_items(hsumma_plan_s& p) {
   }
 }
 
-int ensure_device(hsumma_plan_t p, hs::WorkItem** items) {
-  int dev = 0;
-  HS_CHECK_HIP(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(p->mu);
-  auto it = p->dev.find(dev);
-  if (it != p->dev.end()) {
-    *items = it->second.items;
-    return HSUMMA_OK;
+int check_ws(hsumma_plan_t p, const void* ws, size_t ws_bytes) {
+  if (!ws || ws_bytes < p->ws_bytes) {
+    set_error("workspace missing or smaller than hsumma_workspace_size()");
+    return HSUMMA_ERR_WORKSPACE;
   }
-  DeviceState st;
-  const size_t bytes = std::max<size_t>(1, p->items.size()) * sizeof(hs::WorkItem);
-  HS_CHECK_HIP(hipMalloc((void**)&st.items, bytes));
-  if (!p->items.empty()) {
-    hipError_t e = hipMemcpy(st.items, p->items.data(), p->items.size() * sizeof(hs::WorkItem),
-                             hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      hipFree(st.items);
-      set_error(std::string("hipMemcpy(work items): ") + hipGetErrorString(e));
-      return HSUMMA_ERR_DEVICE;
-    }
+  if (((uintptr_t)ws) & 255) return invalid("workspace must be 256-byte aligned");
+  return HSUMMA_OK;
+}
+
+// Write the plan's work-item table into the workspace (one small kernel).
+int prepare_items(hsumma_plan_t p, void* ws, hipStream_t stream) {
+  if (p->items.empty()) return HSUMMA_OK;
+  uint8_t* w8 = (uint8_t*)ws;
+  hs::ItemGenArgs g;
+  g.m = p->m; g.n = p->n;
+  g.P = p->P; g.Q = p->Q; g.I = p->I; g.J = p->J;
+  g.tm = p->cfg.tm; g.tn = p->cfg.tn; g.br = p->br; g.bc = p->bc;
+  g.dist = p->opts.dist; g.nb = p->nb;
+  g.nitems = (int32_t)p->items.size(); g.per_xcd = p->per_xcd; g.lpt = p->lpt ? 1 : 0;
+  g.items = (hs::WorkItem*)(w8 + p->off_items);
+  g.tmp = (hs::WorkItem*)(w8 + p->off_items_tmp);
+  g.prefix = (int32_t*)(w8 + p->off_prefix);
+  hipError_t e = hs::launch_gen_items(g, stream);
+  if (e != hipSuccess) {
+    set_error(std::string("work-item table launch: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
   }
-  p->dev[dev] = st;
-  *items = st.items;
   return HSUMMA_OK;
 }
 
@@ -235,61 +245,70 @@ int check_operands(hsumma_plan_t p, const double* A, int64_t lda, const double* 
   return HSUMMA_OK;
 }
 
-// Launch the update kernel over k-range [k0, k1) (starting at an inner-step
-// boundary) for every work item.  `slot` indexes the per-panel statistics of
-// the precision form.
-int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
-                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init, int64_t slot,
-                 void* ws, size_t ws_bytes, hipStream_t stream, bool products_only = false) {
-  hs::WorkItem* items = nullptr;
-  int rc = ensure_device(p, &items);
-  if (rc) return rc;
-  if (p->items.empty()) return HSUMMA_OK;
-  int grid = 8 * p->per_xcd;
-  // the slice kernels always run persistent (one workgroup per CU over its
-  // XCD's longest-first item list; measured as fast or faster for BF16)
-  const bool persistent = p->opts.persistent || p->fmt >= 0;
+// Grid of a launch over the plan's items: one workgroup per item, or (the
+// persistent mode, and always for the split forms) as many as the CUs hold.
+int launch_grid(hsumma_plan_t p, bool persistent, int occ, int* grid) {
+  *grid = 8 * p->per_xcd;
   if (persistent) {
     int dev = 0, cus = 0;
     HS_CHECK_HIP(hipGetDevice(&dev));
     HS_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int occ = p->fmt < 0 ? std::max(1, hs::fp64_occupancy(p->cfg)) : 1;
-    grid = std::min<int64_t>(grid, (int64_t)cus * occ);
-    grid = std::max(8, (grid / 8) * 8);
+    *grid = (int)std::min<int64_t>(*grid, (int64_t)cus * std::max(1, occ));
+    *grid = std::max(8, (*grid / 8) * 8);
   }
-  if (p->fmt < 0) {
-    hs::UpdateArgs a;
-    a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
-    a.items = items; a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;
-    a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
-    a.persistent = p->opts.persistent;
-    // direct-to-LDS loads move 16-byte units: every k bound, leading
-    // dimension and column offset must be even and the operands aligned;
-    // the per-lane byte offsets (up to a tile's rows of A, 16 rows of B)
-    // must stay below 2^31
-    const bool dma = !p->opts.staged && hs::fp64_has_dma(p->cfg) && p->items_even &&
-                     !((k0 | k1 | p->b | lda | ldb) & 1) &&
-                     !(((uintptr_t)A | (uintptr_t)B) & 15) &&
-                     (int64_t)p->cfg.tm * lda * 8 < (int64_t(1) << 31) &&
-                     (int64_t)16 * ldb * 8 < (int64_t(1) << 31);
-    hipError_t e = hs::launch_fp64(p->cfg, a, grid, stream, dma);
-    if (e != hipSuccess) {
-      set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));
-      return HSUMMA_ERR_DEVICE;
-    }
-    return HSUMMA_OK;
+  return HSUMMA_OK;
+}
+
+// The FP64 update over k-range [k0, k1) on every item of the table in the
+// workspace, with the macro-tile `cfg`.  `gate`: see UpdateArgs.
+int launch_fp64_range(hsumma_plan_t p, const hs::TileCfg& cfg, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* C, int64_t ldc, int64_t k0,
+                      int64_t k1, int zero_init, bool persistent, const int32_t* gate, void* ws,
+                      hipStream_t stream) {
+  int grid = 0;
+  int rc = launch_grid(p, persistent, hs::fp64_occupancy(cfg), &grid);
+  if (rc) return rc;
+  hs::UpdateArgs a;
+  a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
+  a.items = (const hs::WorkItem*)((uint8_t*)ws + p->off_items);
+  a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;
+  a.k0 = k0; a.k1 = k1; a.bstep = p->b; a.zero_init = zero_init;
+  a.persistent = persistent ? 1 : 0;
+  a.gate = gate;
+  // direct-to-LDS loads move 16-byte units: every k bound, leading
+  // dimension and column offset must be even and the operands aligned;
+  // the per-lane byte offsets (up to a tile's rows of A, 16 rows of B)
+  // must stay below 2^31
+  const bool dma = !p->opts.staged && hs::fp64_has_dma(cfg) && p->items_even &&
+                   !((k0 | k1 | p->b | lda | ldb) & 1) &&
+                   !(((uintptr_t)A | (uintptr_t)B) & 15) &&
+                   (int64_t)cfg.tm * lda * 8 < (int64_t(1) << 31) &&
+                   (int64_t)16 * ldb * 8 < (int64_t(1) << 31);
+  hipError_t e = hs::launch_fp64(cfg, a, grid, stream, dma);
+  if (e != hipSuccess) {
+    set_error(std::string("fp64 update launch: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
   }
+  return HSUMMA_OK;
+}
+
+// Launch the local update over k-range [k0, k1) (starting at an inner-step
+// boundary) for every work item; the table must already be in `ws`.  `slot`
+// indexes the per-panel statistics of the precision form.
+int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init, int64_t slot,
+                 void* ws, hipStream_t stream, bool products_only = false) {
+  if (p->items.empty()) return HSUMMA_OK;
+  if (p->fmt < 0)
+    return launch_fp64_range(p, p->cfg, A, lda, B, ldb, C, ldc, k0, k1, zero_init,
+                             p->opts.persistent != 0, nullptr, ws, stream);
   // ---- precision form: split the panel, then slice products ----------------
-  if (!ws || ws_bytes < p->ws_bytes) {
-    set_error("workspace missing or smaller than hsumma_workspace_size()");
-    return HSUMMA_ERR_WORKSPACE;
-  }
-  if (((uintptr_t)ws) & 255) return invalid("workspace must be 256-byte aligned");
   uint8_t* w8 = (uint8_t*)ws;
-  uint32_t* stats = (uint32_t*)(w8 + p->off_stats) + 2 * slot;
+  uint32_t* stats = (uint32_t*)(w8 + p->off_stats) + hs::kStatWords * slot;
+  int32_t* slices = (int32_t*)(w8 + p->off_slices) + slot;
   hipError_t e = hipSuccess;
   if (!products_only) {
-    e = hs::launch_zero_u32(stats, 2, stream);
+    e = hs::launch_zero_u32(stats, hs::kStatWords, stream);
     if (e != hipSuccess) {
       set_error(std::string("stats clear: ") + hipGetErrorString(e));
       return HSUMMA_ERR_DEVICE;
@@ -309,6 +328,7 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   sa.digB = w8 + p->off_digB; sa.planeB = (int64_t)p->n * sa.Wp;
   sa.eA = (int32_t*)(w8 + p->off_eA); sa.fB = (int32_t*)(w8 + p->off_fB);
   sa.stats = stats;
+  sa.slices_out = slices;
   if (!products_only) {
     e = hs::launch_split(sa, stream);
     if (e != hipSuccess) {
@@ -316,6 +336,9 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
       return HSUMMA_ERR_DEVICE;
     }
   }
+  int grid = 0;
+  int rc = launch_grid(p, true, 1, &grid);
+  if (rc) return rc;
   hs::SliceArgs la;
   la.digA = sa.digA; la.planeA = sa.planeA; la.rowsA = sa.m;
   la.digB = sa.digB; la.planeB = sa.planeB; la.rowsB = sa.n;
@@ -324,23 +347,26 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
     la.bytesA = (uint32_t)(p->opts.max_slices * sa.planeA * esz);
     la.bytesB = (uint32_t)(p->opts.max_slices * sa.planeB * esz);
   }
-  la.eA = sa.eA; la.fB = sa.fB; la.stats = stats;
-  la.slices_out = (int32_t*)(w8 + p->off_slices) + slot;
+  la.eA = sa.eA; la.fB = sa.fB;
+  la.slices = slices;
   la.C = C; la.ldc = ldc;
-  la.items = items; la.nitems = (int32_t)p->items.size(); la.per_xcd = p->per_xcd;
+  la.items = (const hs::WorkItem*)(w8 + p->off_items);
+  la.nitems = (int32_t)p->items.size(); la.per_xcd = p->per_xcd;
   la.Wp = sa.Wp; la.nchunks = sa.Wp / hs::kSplitChunk;
-  la.fixed_s = p->opts.slices; la.smin = p->opts.min_slices; la.smax = p->opts.max_slices;
-  la.tau_bits = p->opts.tau_bits;
-  la.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
-  la.log2w = sa.log2w;
-  la.zero_init = zero_init; la.persistent = persistent ? 1 : 0;
+  la.zero_init = zero_init; la.persistent = 1;
   la.dump = (double*)(w8 + p->off_dump);
   e = hs::launch_slices(p->fmt, la, grid, stream);
   if (e != hipSuccess) {
     set_error(std::string("slice products launch: ") + hipGetErrorString(e));
     return HSUMMA_ERR_DEVICE;
   }
-  return HSUMMA_OK;
+  // A panel the split cannot carry to FP64 accuracy (its modelled need is
+  // beyond max_slices digits, or it holds a non-finite value) is computed by
+  // the FP64 kernel instead, on the same items; the decision is on the device
+  // (slice count 0), so both launches are always issued and exactly one of
+  // them does work.
+  return launch_fp64_range(p, hs::TileCfg{64, 128, 16}, A, lda, B, ldb, C, ldc, k0, k1,
+                           zero_init, true, slices, ws, stream);
 }
 
 // A named range per outer step (host side: it brackets the launches, which
@@ -354,15 +380,63 @@ struct StepRange {
   ~StepRange() { roctxRangePop(); }
 };
 
+// The whole product: the work-item table, then every outer step in order
+// (the first stores instead of accumulating).
 int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
-               double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+               double* C, int64_t ldc, void* ws, hipStream_t stream) {
+  int rc = prepare_items(p, ws, stream);
+  if (rc) return rc;
   const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
   for (int64_t g = 0; g < nouter; ++g) {
     StepRange range(g);
-    int rc = launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[g], p->outer_lo[g + 1],
-                          g == 0 ? 1 : 0, g, ws, ws_bytes, stream);
+    rc = launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[g], p->outer_lo[g + 1],
+                      g == 0 ? 1 : 0, g, ws, stream);
     if (rc) return rc;
   }
+  return HSUMMA_OK;
+}
+
+// Whole product on an explicit workspace, direct or through the plan's graph.
+int run_on(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+           double* C, int64_t ldc, void* ws, hipStream_t s) {
+  if (!p->opts.use_graph || s == nullptr) return run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+
+  // Graph mode: capture the launch sequence (table generation included)
+  // once per (pointers, stream, device) and replay it.
+  std::lock_guard<std::mutex> lk(p->mu);
+  int dev = 0;
+  HS_CHECK_HIP(hipGetDevice(&dev));
+  GraphKey key{A, lda, B, ldb, C, ldc, ws, (void*)s};
+  if (!(p->have_graph && p->gkey == key && p->gdevice == dev)) {
+    if (p->gexec) {
+      hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+      p->have_graph = false;
+    }
+    HS_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc2) {
+      if (graph) hipGraphDestroy(graph);
+      return rc2;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+    e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      p->gexec = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+    p->gkey = key;
+    p->gdevice = dev;
+    p->have_graph = true;
+  }
+  HS_CHECK_HIP(hipGraphLaunch(p->gexec, s));
   return HSUMMA_OK;
 }
 
@@ -469,17 +543,6 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
       return invalid("split form: the digit planes of one operand panel exceed 4 GiB "
                      "(max_slices x rows x padded M x digit bytes); use a smaller outer block M");
     }
-    const int64_t nout = (k + M - 1) / M;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t off = 0;
-    p->off_digA = off; off = al(off + (size_t)(p->opts.max_slices * m * Wp * esz));
-    p->off_digB = off; off = al(off + (size_t)(p->opts.max_slices * n * Wp * esz));
-    p->off_eA = off; off = al(off + (size_t)m * 4);
-    p->off_fB = off; off = al(off + (size_t)n * 4);
-    p->off_stats = off; off = al(off + (size_t)std::max<int64_t>(1, nout) * 8);
-    p->off_slices = off; off = al(off + (size_t)std::max<int64_t>(1, nout) * 4);
-    p->off_dump = off; off = al(off + 64 * sizeof(double));
-    p->ws_bytes = off;
   }
 
   p->rlo = block_bounds(m, P);
@@ -494,20 +557,51 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   }
   p->outer_lo.push_back(k);
   if (k == 0) p->outer_lo.assign(1, 0);
+  if ((int64_t)P * Q > (1 << 24)) {
+    delete p;
+    return invalid("grid of more than 2^24 processors");
+  }
   build_items(*p);
+  if (p->items.size() > (size_t)0x7FFFF000) {
+    delete p;
+    return invalid("more than 2^31 work items (use larger macro-tiles or a smaller problem)");
+  }
+  // Workspace layout: the work-item table (and, for the longest-first order,
+  // its unordered copy), the generator's per-processor prefix sums, then the
+  // precision form's digit planes, exponents, per-panel statistics and slice
+  // counts, and the INT8 kernel's dump area.
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  const size_t nit = p->items.size();
+  p->off_items = off; off = al(off + nit * sizeof(hs::WorkItem));
+  p->off_items_tmp = off; if (p->lpt) off = al(off + nit * sizeof(hs::WorkItem));
+  p->off_prefix = off; off = al(off + ((size_t)P * Q + 1) * 4);
+  if (p->fmt >= 0) {
+    const size_t esz = p->fmt == 0 ? 2 : 1;
+    const size_t Wp = (size_t)p->Wp, sl = (size_t)p->opts.max_slices;
+    const size_t nout = (size_t)std::max<int64_t>(1, (k + M - 1) / M);
+    p->off_digA = off; off = al(off + sl * (size_t)m * Wp * esz);
+    p->off_digB = off; off = al(off + sl * (size_t)n * Wp * esz);
+    p->off_eA = off; off = al(off + (size_t)m * 4);
+    p->off_fB = off; off = al(off + (size_t)n * 4);
+    p->off_stats = off; off = al(off + nout * hs::kStatWords * 4);
+    p->off_slices = off; off = al(off + nout * 4);
+    p->off_dump = off; off = al(off + 64 * sizeof(double));
+  }
+  p->ws_bytes = std::max<size_t>(off, 256);
   *out = p;
   return HSUMMA_OK;
 }
 
 void hsumma_plan_destroy(hsumma_plan_t p) {
   if (!p) return;
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
-  if (p->gexec) hipGraphExecDestroy(p->gexec);
-  for (auto& kv : p->dev) {
-    if (hipSetDevice(kv.first) == hipSuccess) hipFree(kv.second.items);
+  if (p->gexec) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+    if (p->gdevice >= 0 && p->gdevice != cur) hipSetDevice(p->gdevice);
+    hipGraphExecDestroy(p->gexec);
+    if (cur >= 0 && p->gdevice != cur) hipSetDevice(cur);
   }
-  if (cur >= 0) hipSetDevice(cur);
   delete p;
 }
 
@@ -583,8 +677,10 @@ int hsumma_local_update(hsumma_plan_t p, int64_t step, const double* A, int64_t 
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
   if (step < 0 || step >= (int64_t)p->steps.size()) return invalid("step out of range");
+  if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+  if ((rc = prepare_items(p, ws, (hipStream_t)stream))) return rc;
   const StepRec& st = p->steps[step];
-  return launch_range(p, A, lda, B, ldb, C, ldc, st.k0, st.k1, 0, st.outer, ws, ws_bytes,
+  return launch_range(p, A, lda, B, ldb, C, ldc, st.k0, st.k1, 0, st.outer, ws,
                       (hipStream_t)stream);
 }
 
@@ -594,69 +690,54 @@ int hsumma_outer_update(hsumma_plan_t p, int64_t outer, const double* A, int64_t
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
   if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
+  if ((rc = check_ws(p, ws, ws_bytes))) return rc;
   StepRange range(outer);
+  if ((rc = prepare_items(p, ws, (hipStream_t)stream))) return rc;
   return launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1], 0,
-                      outer, ws, ws_bytes, (hipStream_t)stream);
+                      outer, ws, (hipStream_t)stream);
 }
 
-int hsumma_outer_products(hsumma_plan_t p, int64_t outer, double* C, int64_t ldc, void* ws,
+int hsumma_outer_products(hsumma_plan_t p, int64_t outer, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, double* C, int64_t ldc, void* ws,
                           size_t ws_bytes, void* stream) {
   if (!p) return invalid("null plan");
   if (p->fmt < 0) {
     set_error("hsumma_outer_products is for the split forms");
     return HSUMMA_ERR_UNSUPPORTED;
   }
-  if (!C || ldc < p->n || (((uintptr_t)C) & 7)) return invalid("bad C");
+  int rc = check_operands(p, A, lda, B, ldb, C, ldc);
+  if (rc) return rc;
   if (outer < 0 || outer >= (int64_t)p->outer_lo.size() - 1) return invalid("outer step out of range");
-  return launch_range(p, nullptr, 0, nullptr, 0, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1],
-                      0, outer, ws, ws_bytes, (hipStream_t)stream, true);
+  if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+  if ((rc = prepare_items(p, ws, (hipStream_t)stream))) return rc;
+  return launch_range(p, A, lda, B, ldb, C, ldc, p->outer_lo[outer], p->outer_lo[outer + 1], 0,
+                      outer, ws, (hipStream_t)stream, true);
 }
 
 int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
                double* C, int64_t ldc, void* ws, size_t ws_bytes, void* stream) {
   int rc = check_operands(p, A, lda, B, ldb, C, ldc);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  if (!p->opts.use_graph || s == nullptr)
-    return run_direct(p, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
+  if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+  return run_on(p, A, lda, B, ldb, C, ldc, ws, (hipStream_t)stream);
+}
 
-  // Graph mode: capture the launch sequence once per (pointers, stream).
-  hs::WorkItem* items = nullptr;
-  rc = ensure_device(p, &items);  // allocation must happen outside the capture
+int hsumma_prepare_workspace(hsumma_plan_t p, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return invalid("null plan");
+  int rc = check_ws(p, ws, ws_bytes);
   if (rc) return rc;
-  int dev = 0;
-  HS_CHECK_HIP(hipGetDevice(&dev));
-  GraphKey key{A, lda, B, ldb, C, ldc, ws, stream};
-  if (!(p->have_graph && p->gkey == key && p->gdevice == dev)) {
-    if (p->gexec) {
-      hipGraphExecDestroy(p->gexec);
-      p->gexec = nullptr;
-      p->have_graph = false;
-    }
-    HS_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, ws, ws_bytes, s);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &graph);
-    if (rc2) {
-      if (graph) hipGraphDestroy(graph);
-      return rc2;
-    }
-    if (e != hipSuccess) {
-      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-      return HSUMMA_ERR_DEVICE;
-    }
-    e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      p->gexec = nullptr;
-      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      return HSUMMA_ERR_DEVICE;
-    }
-    p->gkey = key;
-    p->gdevice = dev;
-    p->have_graph = true;
+  return prepare_items(p, ws, (hipStream_t)stream);
+}
+
+int hsumma_work_items(hsumma_plan_t p, int32_t* out, int64_t capacity) {
+  if (!p || !out) return invalid("null argument");
+  if (capacity < (int64_t)p->items.size()) return invalid("output smaller than hsumma_num_items()");
+  for (size_t i = 0; i < p->items.size(); ++i) {
+    out[4 * i + 0] = p->items[i].r0;
+    out[4 * i + 1] = p->items[i].c0;
+    out[4 * i + 2] = p->items[i].h;
+    out[4 * i + 3] = p->items[i].w;
   }
-  HS_CHECK_HIP(hipGraphLaunch(p->gexec, s));
   return HSUMMA_OK;
 }
 

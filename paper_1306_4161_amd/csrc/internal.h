@@ -30,7 +30,25 @@ struct UpdateArgs {
   int64_t bstep;       // inner block b: quads restart at every step start
   int32_t zero_init;   // 1: start from C = 0 instead of loading C
   int32_t persistent;  // 1: grid-stride over the items (grouped persistent mode)
+  const int32_t* gate; // non-null: the launch does nothing unless *gate == 0 (the
+                       // split forms' FP64 route for a panel they cannot split)
 };
+
+// Parameters of the device-side work-item generator (k_items.hip).
+struct ItemGenArgs {
+  int64_t m, n;            // rows and columns of C
+  int32_t P, Q, I, J;      // grid and group arrangement
+  int32_t tm, tn;          // macro-tile
+  int32_t br, bc;          // macro-tiles per block inside a processor's tile
+  int32_t dist;            // hsumma_dist
+  int64_t nb;              // block-cyclic block
+  int32_t nitems, per_xcd;
+  int32_t lpt;             // 1: each XCD list in longest-first order
+  WorkItem* items;         // the table (nitems)
+  WorkItem* tmp;           // unordered items (nitems; used when lpt)
+  int32_t* prefix;         // P * Q + 1 item counts, prefix-summed
+};
+hipError_t launch_gen_items(const ItemGenArgs& g, hipStream_t s);
 
 // Workgroup barrier of an LDS ring filled by direct-to-LDS loads.  Each wave
 // first waits (s_waitcnt vmcnt) for its own loads of the stage it is about to

@@ -68,6 +68,7 @@ void fp64_update_kernel(UpdateArgs p) {
   const int b_kk = tid / TN, b_col = tid % TN;
 
   const int k0 = (int)p.k0, k1 = (int)p.k1, bstep = (int)p.bstep;
+  if (p.gate && *p.gate != 0) return;
 
   const int bid = blockIdx.x;
   const int xcd = bid & 7;
@@ -243,6 +244,7 @@ void fp64_dma_kernel(UpdateArgs p) {
   const int wm = wave / WN, wn = wave % WN;
   const int l16 = lane & 15, lq = lane >> 4;
   const int k0 = (int)p.k0, k1 = (int)p.k1, bstep = (int)p.bstep;
+  if (p.gate && *p.gate != 0) return;
 
   const int bid = blockIdx.x, xcd = bid & 7, slot0 = bid >> 3;
   const int slots = p.persistent ? (gridDim.x + 7 - xcd) >> 3 : 1;

@@ -116,28 +116,86 @@ __device__ inline uint8_t e4m3_of_int(int d) {
 // kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
 // the max scaled error of the truncated s-slice product, fitted to the CPU
 // oracle at n = 16384 on uniform and exponent-spread (sigma = 2) entries:
-// log2 err ~ -bits(s) + 0.75 (ka + kb) + 1 - log2(k) / 2 (truncation errors
-// add with random signs over k, (|A||B|)_ij grows like k); bits(s) =
-// H + T (s - 1).  The smallest s whose estimate is within 2^-tau is taken
-// (or the fixed count), clamped to [smin, smax] and to the planes stored.
-// kappa cannot exceed the panel width w, so when ka or kb comes within one
-// bit of log2 w the statistic no longer measures the spread (narrow panels,
-// or lines dominated by one element): such a panel takes smax.
-// The split's digit pass and the product kernels evaluate it identically.
+// log2 err ~ -bits(s) + 0.75 (ka + kb) + 1 - c, bits(s) = H + T (s - 1).
+// The credit c = log2(k) / 2 holds when the truncation errors of the k terms
+// of an entry add with random signs while (|A||B|)_ij grows like k; it is
+// given only when no line's low-order bits repeat: ca, cb are the largest
+// |sum r| / sum |r| over the lines, r the part of each |x| below its 41st
+// significant bit, about 1.2 / sqrt(w) for varied values and 1 for lines
+// of repeated magnitudes (whose dropped digit products then add up
+// coherently).  The smallest s whose estimate is within 2^-tau is taken.
+// kappa cannot exceed the panel width w, so when ka or kb comes within 1.5
+// bits of log2 w (the largest element is over a third of its line's sum) the
+// statistic no longer measures the spread (narrow panels, or lines dominated
+// by one element) and the estimate is only a lower bound.
+// Such a panel takes smax unless the geometric spread says otherwise: la, lb
+// are the largest log2 max|x| - mean log2|x| over the lines (which does not
+// saturate), and the second estimate log2 err ~ -bits(s) + 0.66 (la + lb) +
+// 7.73 - 1.11 log2 k is fitted, like the first, to the CPU oracle's
+// truncated products (exponent spreads sigma = 2 ... 4, k = 64 ... 16384,
+// saturated panels only; largest residual 2.6 bits, hence one bit of margin
+// on top of tau).  If either estimate needs more than smax slices the panel
+// goes to the FP64 kernel.
+// BF16 levels beyond the fourth share one FP32 accumulator that rounds: its
+// error, about 2^-60.5 kappa_A kappa_B / sqrt(k) of (|A||B|)_ij, is above the
+// truncation error of the largest count, so a BF16 panel whose estimate
+// needs more than kBf16RoundBits bits also goes to the FP64 kernel (measured:
+// sigma = 2.5 and 3 panels the truncation model accepts at 7 digits reach
+// 4-6e-14 on the GPU, and 9e-15 two panels outside the saturated band
+// whose estimate was 56.05 bits).
+// Returns 0 -- the panel goes to the FP64 kernel -- when the panel holds a
+// non-finite value (whose IEEE propagation the digits cannot carry) or when
+// the estimate needs more than smax slices.  A fixed count is used as given
+// (non-finite panels still go to the FP64 kernel).
+// The digit pass evaluates it once per panel and stores the result, which
+// the product kernels and the FP64 route read.
+constexpr float kBf16RoundBits = 56.0f;
+
 __device__ __forceinline__ int panel_slices(const uint32_t* stats, int fixed_s, int smin, int smax,
                                             int tau_bits, float log2k, float log2w, int H, int T) {
-  int s = fixed_s;
-  if (s <= 0) {
-    const float ka = __uint_as_float(stats[0]), kb = __uint_as_float(stats[1]);
-    if (fmaxf(ka, kb) >= log2w - 1.0f) {
-      s = smax;
-    } else {
-      const float need = (float)tau_bits + 0.75f * (ka + kb) + 1.0f - 0.5f * log2k;
-      s = (int)ceilf((need - (float)H) / (float)T) + 1;
-    }
-    s = max(smin, min(smax, s));
+  // BF16 is the format with H = 8, T = 9
+  const float cap = (H == 8 && T == 9) ? kBf16RoundBits : 1e30f;
+  if (stats[kStatNonFinite]) return 0;
+  if (fixed_s > 0) return min(kSplitMaxSlices, fixed_s);
+  const int top = min(smax, kSplitMaxSlices);
+  const float ka = __uint_as_float(stats[kStatKappaA]), kb = __uint_as_float(stats[kStatKappaB]);
+  const float coh = fmaxf(__uint_as_float(stats[kStatCohA]), __uint_as_float(stats[kStatCohB]));
+  const bool cancels = log2w >= 6.0f && coh <= fminf(0.75f, 8.0f * exp2f(-0.5f * log2w));
+  const float need =
+      (float)tau_bits + 0.75f * (ka + kb) + 1.0f - (cancels ? 0.5f * log2k : 0.0f);
+  const int s = max(smin, (int)ceilf((need - (float)H) / (float)T) + 1);
+  if (s > top || need > cap) return 0;
+  if (fmaxf(ka, kb) >= log2w - 1.5f) {
+    const float lam = __uint_as_float(stats[kStatLamA]) + __uint_as_float(stats[kStatLamB]);
+    const float need2 =
+        (float)tau_bits + 0.66f * lam + 8.73f - (cancels ? 1.11f * log2k : 0.0f);
+    if ((int)ceilf((need2 - (float)H) / (float)T) + 1 > top || need2 > cap) return 0;
+    return max(1, top);
   }
-  return max(1, min(kSplitMaxSlices, s));
+  return max(1, s);
+}
+
+// log2 |x| for finite nonzero x, from its exponent and mantissa (no underflow
+// to the FP32 range).
+__device__ __forceinline__ float log2_abs(double x) {
+  int e;
+  const double m = frexp(fabs(x), &e);               // [0.5, 1)
+  return (float)e + __log2f((float)m);
+}
+
+// The bits of |x| below its 41st significant bit, as a signed fraction of
+// that bit's unit in [-1/2, 1/2] (0 for 0 and for non-finite x): repeated
+// magnitudes give equal values, varied ones values spread over the interval.
+__device__ __forceinline__ double low_bits(double x) {
+  if (!(fabs(x) <= 1.7976931348623157e308)) return 0.0;
+  int e;
+  const double y = ldexp(frexp(fabs(x), &e), 41);   // exact: mantissa times 2^41
+  return y - rint(y);
+}
+
+// The panel's coherence statistic from one line's sums.
+__device__ __forceinline__ float coherence(double rs, double ra) {
+  return ra > 0.0 ? (float)(fabs(rs) / ra) : 0.0f;
 }
 
 // ---- split: statistics pass, then digit pass; 64 lines per block ------------
@@ -168,7 +226,12 @@ __device__ void split_stats_lines(const SplitArgs& p, int blk) {
   const int line = blk * 64 + lane;
   const bool valid = line < nl;
   const int ln = valid ? line : nl - 1;      // clamped (loads only)
-  double mx = 0.0, sm = 0.0;
+  __shared__ double red_rs[NW][64], red_ra[NW][64];
+  __shared__ float red_lg[NW][64], red_nz[NW][64];
+  __shared__ int red_nf[NW];
+  double mx = 0.0, sm = 0.0, rs = 0.0, ra = 0.0;
+  float lg = 0.0f, nz = 0.0f;                 // sum of log2|x| and count over nonzero x
+  bool nf = false;
   // the next tile's loads are issued before the current tile is reduced
   double x[16], y[16] = {};
   auto load = [&](double* v, int k0) {
@@ -183,23 +246,53 @@ __device__ void split_stats_lines(const SplitArgs& p, int blk) {
     for (int q = 0; q < 16; ++q) {
       mx = fmax(mx, fabs(x[q]));
       sm += fabs(x[q]);
+      const bool fin = fabs(x[q]) <= 1.7976931348623157e308;
+      nf |= !fin;
+      const double r = low_bits(x[q]);
+      rs += r;
+      ra += fabs(r);
+      if (fin && x[q] != 0.0) {
+        lg += log2_abs(x[q]);
+        nz += 1.0f;
+      }
       x[q] = y[q];
     }
   }
   red_mx[wave][lane] = mx;
   red_sm[wave][lane] = sm;
+  red_rs[wave][lane] = rs;
+  red_ra[wave][lane] = ra;
+  red_lg[wave][lane] = lg;
+  red_nz[wave][lane] = nz;
+  const bool wnf = __any(nf && valid);
+  if (lane == 0) red_nf[wave] = wnf ? 1 : 0;
   __syncthreads();
-  if (wave != 0 || !valid) return;
+  if (wave != 0) return;
+  if (lane == 0) {
+    int any = 0;
+    for (int w = 0; w < NW; ++w) any |= red_nf[w];
+    if (any) atomicOr(&p.stats[kStatNonFinite], 1u);
+  }
+  if (!valid) return;
 #pragma unroll
   for (int w = 1; w < NW; ++w) {
     mx = fmax(mx, red_mx[w][lane]);
     sm += red_sm[w][lane];
+    rs += red_rs[w][lane];
+    ra += red_ra[w][lane];
+    lg += red_lg[w][lane];
+    nz += red_nz[w][lane];
   }
   (COLS ? p.fB : p.eA)[line] = exponent_bound(mx);
+  if (nz > 0.0f && mx <= 1.7976931348623157e308) {
+    const float lam = log2_abs(mx) - lg / nz;
+    atomicMax(&p.stats[COLS ? kStatLamB : kStatLamA], __float_as_uint(fmaxf(lam, 0.0f)));
+  }
   if (sm > 0.0) {
     const float kap = (float)log2(mx * (double)p.w / sm);
-    atomicMax(&p.stats[COLS ? 1 : 0], __float_as_uint(fmaxf(kap, 0.0f)));
+    atomicMax(&p.stats[COLS ? kStatKappaB : kStatKappaA], __float_as_uint(fmaxf(kap, 0.0f)));
   }
+  atomicMax(&p.stats[COLS ? kStatCohB : kStatCohA], __float_as_uint(coherence(rs, ra)));
 }
 
 // A rows: the same 64-row x 16-k tiles as the digit pass (lanes along k,
@@ -207,14 +300,22 @@ __device__ void split_stats_lines(const SplitArgs& p, int blk) {
 // over the 8 lanes of a row and then over the waves.
 __device__ void split_stats_rows(const SplitArgs& p, int blk) {
   constexpr int NW = kSplitWaves;
-  __shared__ double red_mx[NW][64], red_sm[NW][64];
+  __shared__ double red_mx[NW][64], red_sm[NW][64], red_rs[NW][64], red_ra[NW][64];
+  __shared__ float red_lg[NW][64], red_nz[NW][64];
+  __shared__ int red_nf[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane >> 3, kp = 2 * (lane & 7);
-  double mx[8], sm[8];
+  double mx[8], sm[8], rs[8], ra[8];
+  float lg[8], nz[8];                         // sum of log2|x| and count over nonzero x
+  bool nf = false;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     mx[i] = 0.0;
     sm[i] = 0.0;
+    rs[i] = 0.0;
+    ra[i] = 0.0;
+    lg[i] = 0.0f;
+    nz[i] = 0.0f;
   }
   // the next tile's loads are issued before the current tile is reduced
   double x[16], y[16] = {};
@@ -236,6 +337,21 @@ __device__ void split_stats_rows(const SplitArgs& p, int blk) {
       const double x0 = fabs(x[2 * i]), x1 = fabs(x[2 * i + 1]);
       mx[i] = fmax(mx[i], fmax(x0, x1));
       sm[i] += x0 + x1;
+      // rows past m are loaded clamped to the last row: no flag from them
+      const bool live = blk * 64 + lr + 8 * i < p.m;
+      // (each value tested alone: fmax would drop a NaN)
+      nf |= live && !(x0 <= 1.7976931348623157e308 && x1 <= 1.7976931348623157e308);
+      const double r0 = low_bits(x[2 * i]), r1 = low_bits(x[2 * i + 1]);
+      rs[i] += r0 + r1;
+      ra[i] += fabs(r0) + fabs(r1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double v = x[2 * i + h];
+        if (v != 0.0 && fabs(v) <= 1.7976931348623157e308) {
+          lg[i] += log2_abs(v);
+          nz[i] += 1.0f;
+        }
+      }
       x[2 * i] = y[2 * i];
       x[2 * i + 1] = y[2 * i + 1];
     }
@@ -245,26 +361,52 @@ __device__ void split_stats_rows(const SplitArgs& p, int blk) {
     for (int o = 1; o < 8; o <<= 1) {
       mx[i] = fmax(mx[i], __shfl_xor(mx[i], o));
       sm[i] += __shfl_xor(sm[i], o);
+      rs[i] += __shfl_xor(rs[i], o);
+      ra[i] += __shfl_xor(ra[i], o);
+      lg[i] += __shfl_xor(lg[i], o);
+      nz[i] += __shfl_xor(nz[i], o);
     }
     if ((lane & 7) == 0) {
       red_mx[wave][lr + 8 * i] = mx[i];
       red_sm[wave][lr + 8 * i] = sm[i];
+      red_rs[wave][lr + 8 * i] = rs[i];
+      red_ra[wave][lr + 8 * i] = ra[i];
+      red_lg[wave][lr + 8 * i] = lg[i];
+      red_nz[wave][lr + 8 * i] = nz[i];
     }
   }
+  const bool wnf = __any(nf);
+  if (lane == 0) red_nf[wave] = wnf ? 1 : 0;
   __syncthreads();
+  if (wave != 0) return;
+  if (lane == 0) {
+    int any = 0;
+    for (int w = 0; w < NW; ++w) any |= red_nf[w];
+    if (any) atomicOr(&p.stats[kStatNonFinite], 1u);
+  }
   const int row = blk * 64 + lane;
-  if (wave != 0 || row >= p.m) return;
-  double m2 = red_mx[0][lane], s2 = red_sm[0][lane];
+  if (row >= p.m) return;
+  double m2 = red_mx[0][lane], s2 = red_sm[0][lane], r2 = red_rs[0][lane], a2 = red_ra[0][lane];
+  float g2 = red_lg[0][lane], z2 = red_nz[0][lane];
 #pragma unroll
   for (int w = 1; w < NW; ++w) {
     m2 = fmax(m2, red_mx[w][lane]);
     s2 += red_sm[w][lane];
+    r2 += red_rs[w][lane];
+    a2 += red_ra[w][lane];
+    g2 += red_lg[w][lane];
+    z2 += red_nz[w][lane];
   }
   p.eA[row] = exponent_bound(m2);
+  if (z2 > 0.0f && m2 <= 1.7976931348623157e308) {
+    const float lam = log2_abs(m2) - g2 / z2;
+    atomicMax(&p.stats[kStatLamA], __float_as_uint(fmaxf(lam, 0.0f)));
+  }
   if (s2 > 0.0) {
     const float kap = (float)log2(m2 * (double)p.w / s2);
-    atomicMax(&p.stats[0], __float_as_uint(fmaxf(kap, 0.0f)));
+    atomicMax(&p.stats[kStatKappaA], __float_as_uint(fmaxf(kap, 0.0f)));
   }
+  atomicMax(&p.stats[kStatCohA], __float_as_uint(coherence(r2, a2)));
 }
 
 __global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs p) {
@@ -406,6 +548,8 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArg
   __shared__ double tiles[kSplitWaves][64 * kTileStride];
   const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w,
                              digit_h(FMT), digit_t(FMT));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p.slices_out = s;
+  if (s == 0) return;                         // the FP64 kernel computes this panel
   const int ga = (p.m + 63) / 64;
   if ((int)blockIdx.x < ga) split_digit_rows<FMT>(p, blockIdx.x, s, tiles[threadIdx.x >> 6]);
   else split_digit_lines<FMT, true>(p, blockIdx.x - ga, s);
@@ -781,8 +925,8 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
 
 __global__ __launch_bounds__(256, 1) void slice_bf16_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w, 8, 9);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
+  const int s = *p.slices;
+  if (s <= 0) return;                          // the FP64 kernel computes this panel
   switch (s) {
     case 1: slice_bf16_items<1>(p, smem); break;
     case 2: slice_bf16_items<2>(p, smem); break;
@@ -990,8 +1134,8 @@ __device__ __forceinline__ void slice_fp8_items(const SliceArgs& p, uint8_t* sme
 
 __global__ __launch_bounds__(256, 1) void slice_fp8_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kFp8Lds];
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w, 4, 5);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
+  const int s = *p.slices;
+  if (s <= 0) return;                          // the FP64 kernel computes this panel
   switch (s) {
     case 1: slice_fp8_items<1>(p, smem); break;
     case 2: slice_fp8_items<2>(p, smem); break;
@@ -1268,9 +1412,8 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
 
 __global__ __launch_bounds__(256, 1) void slice_i8_kernel(SliceArgs p) {
   __shared__ __attribute__((aligned(1024))) uint8_t smem[kBf16Lds];
-  const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w,
-                             digit_h(2), digit_t(2));
-  if (blockIdx.x == 0 && threadIdx.x == 0 && p.slices_out) *p.slices_out = s;
+  const int s = *p.slices;
+  if (s <= 0) return;                          // the FP64 kernel computes this panel
   switch (s) {
     case 1: slice_i8_items<1>(p, smem); break;
     case 2: slice_i8_items<2>(p, smem); break;

@@ -10,6 +10,16 @@ constexpr int kSplitMaxSlices = 8;   // digit planes written per operand (any fo
 constexpr int split_max_slices(int fmt) { return fmt == 2 ? 8 : 7; }
 constexpr int kSplitChunk = 32;      // panel width is padded to a multiple of this
 
+// Per-panel statistics written by the statistics pass (uint32 words):
+constexpr int kStatKappaA = 0;       // max over A rows of log2 kappa (float bits)
+constexpr int kStatKappaB = 1;       // max over B columns of log2 kappa (float bits)
+constexpr int kStatCohA = 2;         // max over A rows of the residual coherence (float bits)
+constexpr int kStatCohB = 3;         // max over B columns of the same
+constexpr int kStatNonFinite = 4;    // nonzero if the panel holds an Inf or a NaN
+constexpr int kStatLamA = 5;         // max over A rows of log2 max|x| - mean log2|x| (float bits)
+constexpr int kStatLamB = 6;         // max over B columns of the same
+constexpr int kStatWords = 8;        // words per panel (padded)
+
 struct SplitArgs {
   const double* A; int64_t lda;      // panel = A(:, k0:k0+w)
   const double* B; int64_t ldb;      // panel = B(k0:k0+w, :)
@@ -19,9 +29,11 @@ struct SplitArgs {
   void* digA; int64_t planeA;        // planes of m x Wp digits (elements per plane)
   void* digB; int64_t planeB;        // planes of n x Wp digits (B transposed)
   int32_t* eA; int32_t* fB;          // per-row / per-column exponents
-  uint32_t* stats;                   // [0]: max log2 kappa over A rows, [1]: over B cols
-  int32_t fixed_s, smin, tau_bits;   // slice-count choice (as in SliceArgs)
-  float log2k, log2w;
+  uint32_t* stats;                   // kStatWords words, cleared before the statistics pass
+  int32_t* slices_out;               // the panel's slice count (0: the FP64 kernel computes it)
+  int32_t fixed_s, smin, tau_bits;   // slice-count choice: fixed count, bounds, target bits
+  float log2k;                       // log2 of the product's inner dimension k
+  float log2w;                       // log2 of the panel width
 };
 
 struct SliceArgs {
@@ -29,13 +41,11 @@ struct SliceArgs {
   const void* digB; int64_t planeB; int32_t rowsB;   // rowsB = n
   uint32_t bytesA, bytesB;           // byte sizes of the two digit regions (< 4 GiB)
   const int32_t* eA; const int32_t* fB;
-  const uint32_t* stats; int32_t* slices_out;
+  const int32_t* slices;             // the panel's slice count, written by the digit pass
+                                     // (0: the launch does nothing)
   double* C; int64_t ldc;
   const WorkItem* items; int32_t nitems; int32_t per_xcd;
   int32_t Wp, nchunks;
-  int32_t fixed_s, smin, smax, tau_bits;
-  float log2k;                       // log2 of the product's inner dimension k
-  float log2w;                       // log2 of the panel width
   int32_t zero_init, persistent;
   double* dump;                      // 64 doubles of workspace: INT8 stores of lanes outside an item
 };

@@ -22,6 +22,7 @@ EXPORTED = [
     "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
     "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
+    "hsumma_work_items", "hsumma_prepare_workspace",
     "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
     "hsumma_mlp_adam", "hsumma_model_bcast", "hsumma_model_cost", "hsumma_model_dcomm_dgroups",
     "hsumma_model_select_groups", "hsumma_model_cost_levels",
@@ -96,7 +97,9 @@ def lib():
         L.hsumma_local_update.argtypes = upd
         L.hsumma_outer_update.argtypes = upd
         L.hsumma_run.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
-        L.hsumma_outer_products.argtypes = [vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        L.hsumma_outer_products.argtypes = upd
+        L.hsumma_work_items.argtypes = [vp, P(i32), i64]
+        L.hsumma_prepare_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.hsumma_panel_slices.argtypes = [vp, vp, P(i32), vp]
         sz = ctypes.c_size_t
         L.hsumma_split_layout.argtypes = [vp, P(sz), P(sz), P(sz), P(sz), P(i32), P(i32)]
@@ -232,12 +235,10 @@ class Plan:
         return dict(zip(keys, [x.value for x in v64 + v32]))
 
     # ---- compute ---------------------------------------------------------
-    def workspace(self):
+    def workspace(self, device="cuda"):
+        """A device workspace of hsumma_workspace_size() bytes (torch owns it)."""
         import torch
-        nbytes = self.workspace_size
-        if nbytes == 0:
-            return None
-        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return torch.empty(self.workspace_size, dtype=torch.uint8, device=device)
 
     def _args(self, A, B, C, ws):
         a, lda = _dev_ptr(A, "A")
@@ -260,11 +261,24 @@ class Plan:
         _check(lib().hsumma_outer_update(self._h, g, a, lda, b, ldb, c, ldc, wsp, wsn,
                                          _stream(stream)))
 
-    def outer_products(self, g, C, ws, stream=None):
+    def outer_products(self, g, A, B, C, ws, stream=None):
         """Split forms: the product launch of outer step g on the planes in ws."""
-        c, ldc = _dev_ptr(C, "C")
-        _check(lib().hsumma_outer_products(self._h, g, c, ldc, ctypes.c_void_p(ws.data_ptr()),
-                                           ws.numel() * ws.element_size(), _stream(stream)))
+        a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)
+        _check(lib().hsumma_outer_products(self._h, g, a, lda, b, ldb, c, ldc, wsp, wsn,
+                                           _stream(stream)))
+
+    def work_items(self):
+        """The plan's work-item table (host): int32 array (items, 4) of r0, c0, h, w."""
+        import numpy as np
+        n = self.num_items
+        out = (ctypes.c_int32 * (4 * max(1, n)))()
+        _check(lib().hsumma_work_items(self._h, out, n))
+        return np.frombuffer(out, dtype=np.int32)[:4 * n].reshape(n, 4).copy()
+
+    def prepare_workspace(self, ws, stream=None):
+        """Write the work-item table into ws (as every compute call does first)."""
+        _check(lib().hsumma_prepare_workspace(self._h, ctypes.c_void_p(ws.data_ptr()),
+                                              ws.numel() * ws.element_size(), _stream(stream)))
 
     def run(self, A, B, C, ws=None, stream=None):
         a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)

@@ -96,7 +96,7 @@ def time_candidate(shape: Shape, opts: dict, A, B, C, reps: int = 3) -> float:
                    **opts)
     ws = plan.workspace()
     stream = torch.cuda.current_stream()
-    plan.outer_update(0, A, B, C, ws=ws)          # warm-up (uploads the work items)
+    plan.outer_update(0, A, B, C, ws=ws)          # warm-up
     times = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -252,7 +252,7 @@ def select_groups_by_sampling(n: int, P: int, Q: int, b: int, M: int, counts=Non
     def run(G):
         for s in range(nsteps):
             plans[G].outer_update(s, A, B, C, ws=wss[G])
-    for G in counts:                        # warm-up: work items uploaded, clocks up
+    for G in counts:                        # warm-up: clocks up
         run(G)
     torch.cuda.synchronize()
     # the counts take turns in every repetition, so that clock or thermal

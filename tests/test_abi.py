@@ -134,7 +134,76 @@ def test_queries_reject_bad_indices():
         p.step_info(8)
     with pytest.raises(hs.HsummaError):
         p.tile_shape(2, 0)
-    assert p.workspace_size == 0
+    # every precision needs a workspace: at least the work-item table
+    assert p.workspace_size >= 16 * p.num_items > 0
+
+
+ITEM_CASES = [
+    # n, P, Q, G, b, M, dist, nb, m, k, extra plan options
+    (384, 3, 3, 3, 16, 64, "block", 0, 0, 0, {}),
+    (1000, 6, 6, 9, 20, 40, "block", 0, 0, 0, {}),
+    (1000, 6, 6, 9, 20, 40, "block", 0, 0, 0, {"persistent": 1}),
+    (10000, 6, 10, 1, 128, 128, "cyclic", 128, 0, 0, {"persistent": 1}),
+    (77, 3, 5, 15, 6, 12, "cyclic", 5, 91, 53, {}),
+    (130, 4, 3, 6, 7, 21, "block", 0, 65, 200, {"persistent": 1}),
+    (768, 3, 4, 6, 32, 128, "block", 0, 0, 0, {"prec": hs.SPLIT_INT8}),
+    (700, 2, 3, 2, 50, 100, "cyclic", 70, 500, 0, {"prec": hs.SPLIT_BF16}),
+    (512, 4, 4, 16, 32, 64, "block", 0, 0, 0, {"tile_m": 32, "tile_n": 32}),
+]
+
+
+@pytest.mark.parametrize("case", ITEM_CASES)
+def test_work_items_cover_c_once_inside_one_tile(case):
+    # The work-item table (Sec. II-A: each processor updates its own block of
+    # C; Sec. III: processors listed group by group): the macro-tiles cover
+    # every entry of C exactly once, each lies in one processor's tile and in
+    # one distribution block, and in the longest-first modes every XCD list
+    # has non-increasing areas.
+    import numpy as np
+    n, P, Q, G, b, M, dist, nb, m, k, extra = case
+    d = hs.DIST_BLOCK if dist == "block" else hs.DIST_BLOCK_CYCLIC
+    p = hs.Plan(n, P, Q, G, b, M, dist=d, nb=nb, m=m, k=k, **extra)
+    m = m or n
+    nbe = nb or b
+    it = p.work_items()
+    assert it.shape == (p.num_items, 4)
+    assert p.workspace_size >= 16 * p.num_items
+    cover = np.zeros((m, n), dtype=np.int32)
+    for r0, c0, h, w in it:
+        assert h > 0 and w > 0
+        cover[r0:r0 + h, c0:c0 + w] += 1
+        pr = plan_ref.owner(r0, m, P, dist, nbe)
+        pc = plan_ref.owner(c0, n, Q, dist, nbe)
+        assert plan_ref.owner(r0 + h - 1, m, P, dist, nbe) == pr
+        assert plan_ref.owner(c0 + w - 1, n, Q, dist, nbe) == pc
+        if dist == "cyclic":
+            assert r0 // nbe == (r0 + h - 1) // nbe and c0 // nbe == (c0 + w - 1) // nbe
+    assert cover.min() == 1 and cover.max() == 1
+    per = (p.num_items + 7) // 8
+    if extra.get("persistent") or extra.get("prec"):
+        for x in range(8):
+            a = it[x * per:(x + 1) * per, 2].astype(np.int64) * it[x * per:(x + 1) * per, 3]
+            assert np.all(a[:-1] >= a[1:])
+    p.close()
+
+
+def test_compute_calls_check_the_workspace_before_launching():
+    # host-side validation: a missing, short or misaligned workspace is
+    # rejected before anything is launched (fake device addresses suffice)
+    import ctypes
+    p = hs.Plan(256, 2, 2, 1, 32)
+    L = hs.lib()
+    A, B, C = (ctypes.c_void_p(0x100000 * (i + 1)) for i in range(3))
+    need = p.workspace_size
+    cases = [(None, need, hs.ERR_WORKSPACE), (0x7000000, need - 1, hs.ERR_WORKSPACE),
+             (0x7000010, need, hs.ERR_INVALID)]
+    for wsp, wsn, code in cases:
+        ws = ctypes.c_void_p(wsp)
+        assert L.hsumma_run(p._h, A, 256, B, 256, C, 256, ws, wsn, None) == code
+        assert L.hsumma_local_update(p._h, 0, A, 256, B, 256, C, 256, ws, wsn, None) == code
+        assert L.hsumma_outer_update(p._h, 0, A, 256, B, 256, C, 256, ws, wsn, None) == code
+        assert L.hsumma_prepare_workspace(p._h, ws, wsn, None) == code
+    p.close()
 
 
 def test_split_plans_validate_slices_panel_and_steps():

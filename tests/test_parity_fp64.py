@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 def _run(plan, A, B, **kw):
     import torch
     C = torch.empty((plan.m, plan.n), dtype=torch.float64, device="cuda")
+    kw.setdefault("ws", plan.workspace())
     plan.run(dev(A) if isinstance(A, np.ndarray) else A,
              dev(B) if isinstance(B, np.ndarray) else B, C, **kw)
     return host(C)
@@ -80,12 +81,13 @@ def test_run_equals_local_updates_and_outer_updates_bitwise():
     p = hs.Plan(n, 3, 3, 3, 16, 64)
     Cr = _run(p, A, B)
     dA, dB = dev(A), dev(B)
+    ws = p.workspace()
     C1 = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     for s in range(p.num_steps):
-        p.local_update(s, dA, dB, C1)
+        p.local_update(s, dA, dB, C1, ws=ws)
     C2 = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     for g in range(p.num_outer_steps):
-        p.outer_update(g, dA, dB, C2)
+        p.outer_update(g, dA, dB, C2, ws=ws)
     assert np.array_equal(host(C1), Cr)
     assert np.array_equal(host(C2), Cr)
 
@@ -98,11 +100,12 @@ def test_prefix_invariant_after_each_step():
     B = inputs.uniform(n, n, 32)
     p = hs.Plan(n, 2, 4, 2, 24, 48)
     dA, dB = dev(A), dev(B)
+    ws = p.workspace()
     C = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     rows, cols = np.meshgrid(np.arange(0, n, 3), np.arange(0, n, 5), indexing="ij")
     rows, cols = rows.ravel(), cols.ravel()
     for s in range(p.num_steps):
-        p.local_update(s, dA, dB, C)
+        p.local_update(s, dA, dB, C, ws=ws)
         e = p.step_info(s)["k1"]
         check_sampled(A[:, :e], B[:e, :], host(C), rows, cols)
 
@@ -182,13 +185,15 @@ def test_c3_block_cyclic_persistent_graph():
     B = inputs.uniform(n, n, inputs.SEED_B)
     p = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, persistent=1, use_graph=1)
     dA, dB = dev(A), dev(B)
+    ws = p.workspace()
     C = torch.empty((n, n), dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
     outs = []
     for rep in range(3):
         with torch.cuda.stream(stream):
             C.fill_(float("nan"))
-            p.run(dA, dB, C, stream=stream)
+            ws.fill_(0xA5)  # the graph regenerates the work-item table on each replay
+            p.run(dA, dB, C, ws=ws, stream=stream)
         stream.synchronize()
         outs.append(host(C))
         dA.add_(0.0)  # eager work between replays

@@ -107,7 +107,9 @@ def test_digit_planes_match_oracle_bitwise(prec, fmt):
     m, k, n, M = 96, 100, 80, 100
     A = inputs.exponent_spread(m, k, 3, sigma=2.0)
     B = inputs.exponent_spread(k, n, 4, sigma=2.0)
-    p = hs.Plan(n, 2, 2, 1, 100, M, m=m, k=k, prec=prec)
+    # the digit planes at a fixed count (the automatic count may send such a
+    # narrow, widely spread panel to the FP64 kernel, which writes no digits)
+    p = hs.Plan(n, 2, 2, 1, 100, M, m=m, k=k, prec=prec, slices=8 if fmt == "int8" else 7)
     C, ws = _run(p, A, B)
     lay = p.split_layout()
     Wp, planes = lay["Wp"], lay["planes"]
@@ -325,7 +327,8 @@ def test_degenerate_shapes_meet_gate(shape, prec):
     err = np.abs(C[rows, cols] - c) / np.where(s > 0, s, 1.0)
     slices = p.panel_slices(ws)
     _say("  slices %r max scaled err %.3g" % (slices, err.max()))
-    assert all(3 <= x <= (8 if prec == hs.SPLIT_INT8 else 7) for x in slices)
+    # 0: the panel went to the FP64 kernel
+    assert all(x == 0 or 3 <= x <= (8 if prec == hs.SPLIT_INT8 else 7) for x in slices)
     assert err.max() <= GATE
 
 
@@ -346,6 +349,7 @@ def test_c3_block_cyclic_split_graph(prec):
     for rep in range(3):
         with torch.cuda.stream(stream):
             C.fill_(float("nan"))
+            ws.fill_(0xA5)  # the graph regenerates the work-item table on each replay
             p.run(dA, dB, C, ws=ws, stream=stream)
         stream.synchronize()
         outs.append(host(C))
@@ -362,3 +366,133 @@ def test_c3_block_cyclic_split_graph(prec):
     # the launch without the graph gives the same bits
     q = hs.Plan(n, 6, 10, 1, 128, dist=hs.DIST_BLOCK_CYCLIC, prec=prec)
     assert np.array_equal(_run(q, dA, dB)[0], Cn)
+
+
+# ------------------------------------------------------- the FP64 route --
+# A panel the split cannot carry to FP64 accuracy goes to the FP64 kernel
+# (slice count 0): a non-finite value in the panel, or a modelled need above
+# max_slices digits.  The FP64 kernel's sums do not depend on the
+# macro-tile, so such a panel gives the FP64 path's bits.
+
+def _fp64_reference(n, P, Q, G, b, M, A, B, **kw):
+    import torch
+    p = hs.Plan(n, P, Q, G, b, M, **kw)
+    C = torch.empty((p.m, p.n), dtype=torch.float64, device="cuda")
+    p.run(A, B, C, ws=p.workspace())
+    return host(C)
+
+
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8, hs.SPLIT_FP8])
+def test_need_beyond_max_slices_takes_fp64_route(prec):
+    _say("case route: need beyond max_slices prec=%d" % prec)
+    n, P, Q, G, b, M = 512, 2, 2, 4, 64, 256
+    A = dev(inputs.exponent_spread(n, n, 131, 2.0))
+    B = dev(inputs.exponent_spread(n, n, 132, 2.0))
+    p = hs.Plan(n, P, Q, G, b, M, prec=prec, max_slices=3)   # 3 digits never suffice
+    C, ws = _run(p, A, B)
+    assert p.panel_slices(ws) == [0, 0]
+    assert np.array_equal(C, _fp64_reference(n, P, Q, G, b, M, A, B))
+
+
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+def test_nonfinite_values_take_fp64_route(prec):
+    import torch
+    _say("case route: non-finite prec=%d" % prec)
+    n, P, Q, G, b, M = 384, 3, 2, 6, 32, 128
+    A = inputs.uniform(n, n, 141)
+    B = inputs.uniform(n, n, 142)
+    A[5, 10] = np.nan                # panel 0
+    B[300, 7] = np.inf               # panel 2
+    A[200, 301] = -np.inf            # panel 2
+    dA, dB = dev(A), dev(B)
+    p = hs.Plan(n, P, Q, G, b, M, prec=prec)
+    C, ws = _run(p, dA, dB)
+    sl = p.panel_slices(ws)
+    assert sl[0] == 0 and sl[2] == 0 and sl[1] > 0
+    ref = _fp64_reference(n, P, Q, G, b, M, dA, dB)
+    # every non-finite entry of the FP64 product is the same non-finite
+    # value here: row 5 NaN, column 7 +-Inf or NaN, row 200 -Inf or NaN
+    bad = ~np.isfinite(ref)
+    assert bad[5].all() and bad[:, 7].all() and bad[200].all()
+    assert np.array_equal(np.isnan(C), np.isnan(ref))
+    assert np.array_equal(C[bad & ~np.isnan(ref)], ref[bad & ~np.isnan(ref)])
+    # the finite entries meet the gate
+    good = np.argwhere(~bad)[::97]
+    rows, cols = good[:, 0], good[:, 1]
+    c, s = core.sampled(A, B, rows, cols)
+    assert np.max(np.abs(C[rows, cols] - c) / s) <= GATE
+    # with every panel holding a NaN the whole product is the FP64 path's
+    A2 = A.copy()
+    A2[0, ::M] = np.nan
+    dA2 = dev(A2)
+    C2, ws2 = _run(p, dA2, dB)
+    assert p.panel_slices(ws2) == [0, 0, 0]
+    ref2 = _fp64_reference(n, P, Q, G, b, M, dA2, dB)
+    assert np.array_equal(np.isnan(C2), np.isnan(ref2))
+    fin = np.isfinite(ref2)
+    assert np.array_equal(C2[fin], ref2[fin])
+
+
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+@pytest.mark.parametrize("kind", ["third", "tenth", "signed_third_gram"])
+@pytest.mark.parametrize("k", [1024, 4096])
+def test_repeated_magnitudes_meet_gate(kind, prec, k):
+    # Lines of one repeated magnitude: the digits' truncation errors of every
+    # term have the same sign, so no cancellation over k may be credited.
+    _say("case repeated magnitudes %s prec=%d k=%d" % (kind, prec, k))
+    m = n = 256
+    if kind == "third":
+        A = np.full((m, k), 1.0 / 3.0); B = np.full((k, n), 1.0 / 3.0)
+    elif kind == "tenth":
+        A = np.full((m, k), 0.1); B = np.full((k, n), 0.1)
+    else:
+        # C = S S^T with S = +-1/3: the diagonal sums k equal products
+        S = np.where(inputs.rademacher(m * k, 151).reshape(m, k) > 0, 1.0, -1.0) / 3.0
+        A = S; B = np.ascontiguousarray(S.T[:, :n])
+    p = hs.Plan(n, 2, 2, 1, 256, 256, m=m, k=k, prec=prec)
+    C, ws = _run(p, A, B)
+    rows, cols = np.meshgrid(np.arange(0, m, 7), np.arange(0, n, 5), indexing="ij")
+    rows, cols = np.concatenate([rows.ravel(), np.arange(n)]), np.concatenate([cols.ravel(), np.arange(n)])
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / s
+    _say("  slices %r max scaled err %.3g" % (sorted(set(p.panel_slices(ws))), err.max()))
+    assert err.max() <= GATE
+
+
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+@pytest.mark.parametrize("sigma,k", [(2.0, 4096), (2.5, 1024), (2.5, 4096), (3.0, 64),
+                                     (3.0, 256), (3.0, 1024), (3.0, 4096), (4.0, 1024)])
+def test_wide_spreads_meet_gate(sigma, k, prec):
+    # Exponent spreads beyond sigma = 2 saturate the arithmetic spread
+    # statistic on every panel; the geometric one decides between the
+    # largest slice count and the FP64 route, and every entry meets the gate.
+    _say("case wide spread sigma=%g k=%d prec=%d" % (sigma, k, prec))
+    m = n = 96
+    M = min(k, 1024)
+    A = inputs.exponent_spread(m, k, 121 + k, sigma)
+    B = inputs.exponent_spread(k, n, 122 + k, sigma)
+    p = hs.Plan(n, 1, 1, 1, M, M, m=m, k=k, prec=prec)
+    C, ws = _run(p, A, B)
+    rows, cols = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    rows, cols = rows.ravel(), cols.ravel()
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / s
+    _say("  slices %r max scaled err %.3g" % (p.panel_slices(ws), err.max()))
+    assert err.max() <= GATE
+
+
+@pytest.mark.parametrize("prec", [hs.SPLIT_BF16, hs.SPLIT_INT8])
+def test_sigma3_at_n4096_meets_gate(prec):
+    _say("case sigma=3 n=4096 prec=%d" % prec)
+    n = 4096
+    A = inputs.exponent_spread(n, n, inputs.SEED_A, 3.0)
+    B = inputs.exponent_spread(n, n, inputs.SEED_B, 3.0)
+    p = hs.Plan(n, 4, 4, 4, 256, 1024, prec=prec)
+    C, ws = _run(p, A, B)
+    edges = [i * n // 4 for i in range(4)]
+    rows, cols = inputs.sample_entries(n, n, 2048, inputs.SEED_SAMPLE, edges, edges, per_edge=8)
+    c, s = core.sampled(A, B, rows, cols)
+    err = np.abs(C[rows, cols] - c) / s
+    _say("  slices %r max scaled err %.3g" % (p.panel_slices(ws), err.max()))
+    assert err.max() <= GATE
+    check_freivalds(A, B, C, seeds=(1,))
