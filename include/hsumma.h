@@ -217,6 +217,26 @@ int hsumma_run(hsumma_plan_t plan, const double* A, int64_t lda, const double* B
                int64_t ldb, double* C, int64_t ldc, void* ws, size_t ws_bytes,
                void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as hsumma_run, with the workspace taken from a scratch array the
+ * library holds in device memory (hsumma_noalloc_max_workspace() bytes per
+ * device, held from the library's load on that device until the process
+ * ends).  The call allocates nothing and takes no workspace argument; it
+ * always launches directly (opts.use_graph is ignored: instantiating a graph
+ * may allocate).  A plan whose hsumma_workspace_size() exceeds the scratch
+ * array is rejected with HSUMMA_ERR_WORKSPACE before anything is launched.
+ * Every such call on one device uses that device's one array: calls that
+ * overlap on a device (other streams, other threads) race and must be
+ * ordered by the caller.  Each call rewrites or clears everything it reads
+ * there, so results do not depend on earlier calls.
+ */
+int hsumma_run_noalloc(hsumma_plan_t plan, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, double* C, int64_t ldc, void* stream);
+/* Bytes of the scratch array behind hsumma_run_noalloc (64 MiB). */
+size_t hsumma_noalloc_max_workspace(void);
+
 /* Slice count chosen for each outer panel by the last split-form call
  * (copied to host; synchronises `stream`).  counts has num_outer_steps room.
  * A count of 0 means the panel was computed by the FP64 kernel: it held an

@@ -440,6 +440,41 @@ int run_on(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64
   return HSUMMA_OK;
 }
 
+// ---- workspace for callers that cannot allocate ------------------------------
+// A file-scope device array stands in for the caller's workspace in
+// hsumma_run_noalloc.  Each device holds its own copy from the moment the
+// library's code object is loaded on it until the process ends.  Host code
+// must not use the array's name as an address: the device address is taken
+// once per device with hipGetSymbolAddress (that device current) and used
+// for every kernel argument.  Every call on one device shares the array, so
+// such calls must not overlap on that device (they race); each call rewrites
+// what it reads (work-item table, digit planes) and clears what must start
+// at zero (the per-panel statistics, by kernel), so it does not depend on
+// what an earlier call left there.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device id; null until first use
+
+int scratch_address(void** out) {
+  int dev = 0;
+  HS_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HS_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || (((uintptr_t)ptr) & 255)) {
+      set_error("scratch array: unexpected device address");
+      return HSUMMA_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HSUMMA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -721,6 +756,23 @@ int hsumma_run(hsumma_plan_t p, const double* A, int64_t lda, const double* B, i
   if ((rc = check_ws(p, ws, ws_bytes))) return rc;
   return run_on(p, A, lda, B, ldb, C, ldc, ws, (hipStream_t)stream);
 }
+
+int hsumma_run_noalloc(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, double* C, int64_t ldc, void* stream) {
+  int rc = check_operands(p, A, lda, B, ldb, C, ldc);
+  if (rc) return rc;
+  if (p->ws_bytes > kScratchBytes) {
+    set_error("hsumma_run_noalloc: the plan needs " + std::to_string(p->ws_bytes) +
+              " bytes of workspace, more than the library's " +
+              std::to_string(kScratchBytes) + "-byte scratch array; use hsumma_run");
+    return HSUMMA_ERR_WORKSPACE;
+  }
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return run_direct(p, A, lda, B, ldb, C, ldc, ws, (hipStream_t)stream);
+}
+
+size_t hsumma_noalloc_max_workspace(void) { return kScratchBytes; }
 
 int hsumma_prepare_workspace(hsumma_plan_t p, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return invalid("null plan");

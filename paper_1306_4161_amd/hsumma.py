@@ -22,7 +22,8 @@ EXPORTED = [
     "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
     "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
-    "hsumma_work_items", "hsumma_prepare_workspace",
+    "hsumma_work_items", "hsumma_prepare_workspace", "hsumma_run_noalloc",
+    "hsumma_noalloc_max_workspace",
     "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
     "hsumma_mlp_adam", "hsumma_model_bcast", "hsumma_model_cost", "hsumma_model_dcomm_dgroups",
     "hsumma_model_select_groups", "hsumma_model_cost_levels",
@@ -100,6 +101,8 @@ def lib():
         L.hsumma_outer_products.argtypes = upd
         L.hsumma_work_items.argtypes = [vp, P(i32), i64]
         L.hsumma_prepare_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.hsumma_run_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp]
+        L.hsumma_noalloc_max_workspace.argtypes = []
         L.hsumma_panel_slices.argtypes = [vp, vp, P(i32), vp]
         sz = ctypes.c_size_t
         L.hsumma_split_layout.argtypes = [vp, P(sz), P(sz), P(sz), P(sz), P(i32), P(i32)]
@@ -126,6 +129,7 @@ def lib():
             if name not in ("hsumma_opts_default", "hsumma_plan_destroy",
                             "hsumma_last_error", "hsumma_version"):
                 getattr(L, name).restype = ctypes.c_int
+        L.hsumma_noalloc_max_workspace.restype = ctypes.c_size_t
         L.hsumma_mlp_param_count.restype = i64
         L.hsumma_mlp_work_floats.restype = i64
         _lib = L
@@ -283,6 +287,11 @@ class Plan:
     def run(self, A, B, C, ws=None, stream=None):
         a, lda, b, ldb, c, ldc, wsp, wsn = self._args(A, B, C, ws)
         _check(lib().hsumma_run(self._h, a, lda, b, ldb, c, ldc, wsp, wsn, _stream(stream)))
+
+    def run_noalloc(self, A, B, C, stream=None):
+        """C = A x B with the library's scratch array as workspace (no allocation)."""
+        a, lda, b, ldb, c, ldc, _, _ = self._args(A, B, C, None)
+        _check(lib().hsumma_run_noalloc(self._h, a, lda, b, ldb, c, ldc, _stream(stream)))
 
     def panel_slices(self, ws, stream=None):
         n = self.num_outer_steps

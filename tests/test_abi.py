@@ -235,3 +235,17 @@ def test_split_plans_validate_slices_panel_and_steps():
     for prec, kc in ((hs.SPLIT_INT8, 16), (hs.SPLIT_BF16, 32)):
         with pytest.raises(hs.HsummaError):
             hs.Plan(n, 2, 2, 1, 64, M, prec=prec, kc=kc)
+
+
+def test_noalloc_rejects_a_plan_beyond_its_scratch_array():
+    # host-side: the check precedes any device call (fake device addresses)
+    import ctypes
+    L = hs.lib()
+    limit = L.hsumma_noalloc_max_workspace()
+    assert limit == 64 << 20
+    big = hs.Plan(16384, 16, 16, 16, 256, 1024, prec=hs.SPLIT_INT8)
+    assert big.workspace_size > limit
+    A, B, C = (ctypes.c_void_p(0x100000 * (i + 1)) for i in range(3))
+    assert L.hsumma_run_noalloc(big._h, A, 16384, B, 16384, C, 16384, None) == hs.ERR_WORKSPACE
+    assert "scratch" in L.hsumma_last_error().decode()
+    big.close()
