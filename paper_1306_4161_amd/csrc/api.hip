@@ -84,7 +84,7 @@ struct hsumma_plan_s {
   bool items_even = false;     // every work item starts at an even column, has even width
   // workspace layout (byte offsets): the work-item table (every precision),
   // then the precision form's digit planes, exponents and statistics
-  size_t off_items = 0, off_items_tmp = 0, off_prefix = 0;
+  size_t off_items = 0, off_items_tmp = 0;
   int32_t fmt = -1;            // -1: FP64 path; 0: BF16, 1: FP8-e4m3, 2: INT8 digits
   int32_t Wp = 0;              // padded panel width
   size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_stats = 0, off_slices = 0,
@@ -147,7 +147,9 @@ int64_t local_count(const hsumma_plan_s& p, bool rows, int r) {
   return c;
 }
 
-void build_items(hsumma_plan_s& p) {
+// max_row_block: the largest br x (pieces of a processor column), the
+// generator's int32 unit of a block row.
+void build_items(hsumma_plan_s& p, int64_t* max_row_block) {
   const int gp = p.P / p.I, gq = p.Q / p.J;
   std::vector<std::vector<Run>> rpieces(p.P), cpieces(p.Q);
   for (int r = 0; r < p.P; ++r)
@@ -167,6 +169,9 @@ void build_items(hsumma_plan_s& p) {
   const int br = std::max(1, conc / bc);
   p.br = br;
   p.bc = bc;
+  *max_row_block = 0;
+  for (int c = 0; c < p.Q; ++c)
+    *max_row_block = std::max<int64_t>(*max_row_block, (int64_t)br * cpieces[c].size());
   p.items.clear();
   for (int x = 0; x < p.I; ++x)
     for (int y = 0; y < p.J; ++y)
@@ -225,7 +230,6 @@ int prepare_items(hsumma_plan_t p, void* ws, hipStream_t stream) {
   g.nitems = (int32_t)p->items.size(); g.per_xcd = p->per_xcd; g.lpt = p->lpt ? 1 : 0;
   g.items = (hs::WorkItem*)(w8 + p->off_items);
   g.tmp = (hs::WorkItem*)(w8 + p->off_items_tmp);
-  g.prefix = (int32_t*)(w8 + p->off_prefix);
   hipError_t e = hs::launch_gen_items(g, stream);
   if (e != hipSuccess) {
     set_error(std::string("work-item table launch: ") + hipGetErrorString(e));
@@ -592,25 +596,26 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   }
   p->outer_lo.push_back(k);
   if (k == 0) p->outer_lo.assign(1, 0);
-  if ((int64_t)P * Q > (1 << 24)) {
+  if ((int64_t)P * Q > hs::kGenMaxProcs) {
     delete p;
-    return invalid("grid of more than 2^24 processors");
+    return invalid("grid of more than " + std::to_string(hs::kGenMaxProcs) +
+                   " virtual processors (the work-item generator keeps one count per "
+                   "processor on chip)");
   }
-  build_items(*p);
-  if (p->items.size() > (size_t)0x7FFFF000) {
+  int64_t max_row_block = 0;
+  build_items(*p, &max_row_block);
+  if (p->items.size() > (size_t)0x7FFFF000 || max_row_block >= (int64_t(1) << 31)) {
     delete p;
     return invalid("more than 2^31 work items (use larger macro-tiles or a smaller problem)");
   }
   // Workspace layout: the work-item table (and, for the longest-first order,
-  // its unordered copy), the generator's per-processor prefix sums, then the
-  // precision form's digit planes, exponents, per-panel statistics and slice
-  // counts, and the INT8 kernel's dump area.
+  // its unordered copy), then the precision form's digit planes, exponents,
+  // per-panel statistics and slice counts, and the INT8 kernel's dump area.
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t off = 0;
   const size_t nit = p->items.size();
   p->off_items = off; off = al(off + nit * sizeof(hs::WorkItem));
   p->off_items_tmp = off; if (p->lpt) off = al(off + nit * sizeof(hs::WorkItem));
-  p->off_prefix = off; off = al(off + ((size_t)P * Q + 1) * 4);
   if (p->fmt >= 0) {
     const size_t esz = p->fmt == 0 ? 2 : 1;
     const size_t Wp = (size_t)p->Wp, sl = (size_t)p->opts.max_slices;

@@ -34,7 +34,9 @@ struct UpdateArgs {
                        // split forms' FP64 route for a panel they cannot split)
 };
 
-// Parameters of the device-side work-item generator (k_items.hip).
+// Parameters of the device-side work-item generator (k_items.hip), which
+// keeps one prefix sum per virtual processor in LDS.
+constexpr int kGenMaxProcs = 16384;
 struct ItemGenArgs {
   int64_t m, n;            // rows and columns of C
   int32_t P, Q, I, J;      // grid and group arrangement
@@ -46,7 +48,6 @@ struct ItemGenArgs {
   int32_t lpt;             // 1: each XCD list in longest-first order
   WorkItem* items;         // the table (nitems)
   WorkItem* tmp;           // unordered items (nitems; used when lpt)
-  int32_t* prefix;         // P * Q + 1 item counts, prefix-summed
 };
 hipError_t launch_gen_items(const ItemGenArgs& g, hipStream_t s);
 
