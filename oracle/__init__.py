@@ -18,6 +18,8 @@ Modules
             Ozaki-style error-free split; not in the paper) and the exact
             value of the truncated split product.
   mlp_ref   float64 forward/backward of the small cost-model network.
+  lu_ref    LU factorisation without pivoting by textbook elimination (the
+            workload whose trailing update is the local update).
 
 Parity status per function is stated in each module header.
 """
