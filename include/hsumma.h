@@ -273,6 +273,31 @@ int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k
                             void* stream);
 
 /*
+ * LU factorisation without pivoting, A = L U in place, with the trailing-
+ * matrix update done by the HSUMMA local update (Sec. VI names LU as a
+ * workload for the hierarchical panel updates; the trailing update A22 -=
+ * L21 U12 is the update C += A_panel x B_panel of Sec. II-A).  Blocked with
+ * the two block sizes of Sec. III: outer panels of M columns factored in
+ * inner blocks of b <= 64 columns (M a multiple of b); after each outer
+ * panel the trailing matrix takes one HSUMMA outer update with k = M on the
+ * P x Q grid with G groups (clamped to the trailing block's size), in the
+ * precision of opts.prec (FP64 or a split form).  L (unit lower, without its
+ * diagonal) and U overwrite A (row-major, n x n, leading dimension lda >= n).
+ * No pivoting: the caller guarantees nonzero leading principal minors (e.g.
+ * a diagonally dominant matrix); a zero pivot yields Inf or NaN in the
+ * factors.  The plan is host memory; ws (hsumma_lu_workspace_size() bytes,
+ * 256-byte aligned) holds the negated panel L21 (n x M doubles) and the
+ * trailing updates' workspace.  Asynchronous on `stream`.
+ */
+typedef struct hsumma_lu_plan_s* hsumma_lu_plan_t;
+int hsumma_lu_plan(hsumma_lu_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, int64_t b,
+                   int64_t M, const hsumma_opts* opts);
+int hsumma_lu_workspace_size(hsumma_lu_plan_t plan, size_t* bytes);
+int hsumma_lu(hsumma_lu_plan_t plan, double* A, int64_t lda, void* ws, size_t ws_bytes,
+              void* stream);
+void hsumma_lu_plan_destroy(hsumma_lu_plan_t plan);
+
+/*
  * Communication-cost model of the distributed algorithm (Sec. IV) and the
  * choice of G it implies.  Host only (no device work, no allocation).
  *

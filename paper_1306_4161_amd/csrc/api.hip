@@ -272,7 +272,7 @@ int launch_fp64_range(hsumma_plan_t p, const hs::TileCfg& cfg, const double* A, 
   int grid = 0;
   int rc = launch_grid(p, persistent, hs::fp64_occupancy(cfg), &grid);
   if (rc) return rc;
-  hs::UpdateArgs a;
+  hs::UpdateArgs a{};
   a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
   a.items = (const hs::WorkItem*)((uint8_t*)ws + p->off_items);
   a.nitems = (int32_t)p->items.size(); a.per_xcd = p->per_xcd;

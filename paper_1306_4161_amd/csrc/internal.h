@@ -32,6 +32,9 @@ struct UpdateArgs {
   int32_t persistent;  // 1: grid-stride over the items (grouped persistent mode)
   const int32_t* gate; // non-null: the launch does nothing unless *gate == 0 (the
                        // split forms' FP64 route for a panel they cannot split)
+  // items == nullptr: the items are the macro-tiles of one dense
+  // dense_m x dense_n block of C, row-major over dense_nc tile columns
+  int32_t dense_m, dense_n, dense_nc;
 };
 
 // Parameters of the device-side work-item generator (k_items.hip), which
@@ -74,6 +77,12 @@ const std::vector<TileCfg>& fp64_configs();
 hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s,
                        bool dma);
 bool fp64_has_dma(const TileCfg& cfg);
+// C (m x n, ldc) += A (m x k) B (k x n) by the FP64 update kernel over the
+// macro-tiles of C in row-major order (no work-item table): for updates of
+// one dense block, e.g. inside an LU panel.
+hipError_t launch_fp64_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
+                             double* C, int64_t ldc, int64_t m, int64_t n, int64_t k,
+                             hipStream_t s);
 int fp64_occupancy(const TileCfg& cfg);  // workgroups per CU the config is built for
 
 // Split (precision) path.

@@ -52,6 +52,15 @@ struct Fp64Tile {
   static_assert(KC % 4 == 0, "chunk is whole MFMA k-groups");
 };
 
+// Work item idx: from the table, or the idx-th macro-tile (row-major) of
+// the dense block when there is no table.
+template <int TM, int TN>
+__device__ __forceinline__ WorkItem fetch_item(const UpdateArgs& p, int idx) {
+  if (p.items) return p.items[idx];
+  const int tr = idx / p.dense_nc, tc = idx - tr * p.dense_nc;
+  return WorkItem{tr * TM, tc * TN, min(TM, p.dense_m - tr * TM), min(TN, p.dense_n - tc * TN)};
+}
+
 template <int TM, int TN, int KC, int WM, int WN, int OCC>
 __global__ __launch_bounds__(WM * WN * 64, OCC)
 void fp64_update_kernel(UpdateArgs p) {
@@ -80,7 +89,7 @@ void fp64_update_kernel(UpdateArgs p) {
     if (slot >= p.per_xcd) break;
     const int idx = xcd * p.per_xcd + slot;
     if (idx >= p.nitems) break;
-    const WorkItem it = p.items[idx];
+    const WorkItem it = fetch_item<TM, TN>(p, idx);
     const bool full_tile = (it.h == TM) && (it.w == TN);
     const double* __restrict__ Ab = p.A + (int64_t)it.r0 * p.lda;
     const double* __restrict__ Bb = p.B + it.c0;
@@ -254,7 +263,7 @@ void fp64_dma_kernel(UpdateArgs p) {
     if (slot >= p.per_xcd) break;
     const int idx = xcd * p.per_xcd + slot;
     if (idx >= p.nitems) break;
-    const WorkItem it = p.items[idx];
+    const WorkItem it = fetch_item<TM, TN>(p, idx);
     const bool full_tile = (it.h == TM) && (it.w == TN);
     const double* Ab = p.A + (int64_t)it.r0 * p.lda;
     const double* Bb = p.B + it.c0;
@@ -490,6 +499,26 @@ bool fp64_has_dma(const TileCfg& cfg) {
   for (auto& e : dma_table())
     if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) return true;
   return false;
+}
+
+hipError_t launch_fp64_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
+                             double* C, int64_t ldc, int64_t m, int64_t n, int64_t k,
+                             hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const TileCfg cfg = (m < 512 || n < 512) ? TileCfg{64, 64, 16} : TileCfg{128, 128, 16};
+  UpdateArgs a{};
+  a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
+  a.items = nullptr;
+  a.dense_m = (int32_t)m; a.dense_n = (int32_t)n;
+  a.dense_nc = (int32_t)((n + cfg.tn - 1) / cfg.tn);
+  const int64_t nit = (int64_t)((m + cfg.tm - 1) / cfg.tm) * a.dense_nc;
+  a.nitems = (int32_t)nit;
+  a.per_xcd = (int32_t)((nit + 7) / 8);
+  a.k0 = 0; a.k1 = k; a.bstep = k; a.zero_init = 0; a.persistent = 0; a.gate = nullptr;
+  const bool dma = !((k | lda | ldb) & 1) && !(((uintptr_t)A | (uintptr_t)B) & 15) &&
+                   (int64_t)cfg.tm * lda * 8 < (int64_t(1) << 31) &&
+                   (int64_t)16 * ldb * 8 < (int64_t(1) << 31) && !(n & 1);
+  return launch_fp64(cfg, a, 8 * a.per_xcd, s, dma);
 }
 
 hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStream_t s,

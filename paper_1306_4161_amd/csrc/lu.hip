@@ -1,0 +1,269 @@
+// LU factorisation without pivoting whose trailing-matrix update is the
+// HSUMMA local update -- the second workload the paper names for its
+// hierarchical panel updates (Sec. VI).
+//
+// A = L U in place (L unit lower, strictly below the diagonal; U upper), by
+// blocked elimination with the two block sizes of Sec. III: outer panels of
+// M columns, each factored in inner blocks of b columns.  For outer panel
+// [J, J + w) and each inner block [j, j + v) of it:
+//   1. factor the v x v diagonal block (textbook elimination) and solve
+//      L21 = A21 U11^-1 for every row below it (lu_panel_kernel); -L21 is
+//      also written to the workspace, so the updates below are C += A B;
+//   2. U12 = L11^-1 A12 for every column right of the block
+//      (lu_row_solve_kernel);
+//   3. the update inside the outer panel, A[j+v:, j+v:J+w] -= L21 U12, and
+//      on the outer panel's own rows right of it, A[j+v:J+w, J+w:] -= L U12
+//      (dense FP64 updates, k = v).
+// Then the trailing matrix A[J+w:, J+w:] -= L21 U12 with k = w is one
+// HSUMMA outer update on the P x Q grid with G groups (any precision form):
+// C is loaded once, held in MFMA accumulators across the w/b inner steps
+// and stored once -- the outer block's role on one GPU.
+//
+// No pivoting: the caller guarantees nonzero leading principal minors (e.g.
+// a diagonally dominant matrix); a zero pivot gives Inf or NaN factors.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace hs {
+
+constexpr int kLuMaxB = 64;          // inner block: the diagonal block lives in LDS
+constexpr int kLuThreads = 256;
+
+// Factor the v x v diagonal block at (j, j) in LDS, then for the rows
+// j + v + 256 * blockIdx.x + thread: L21 row = A21 row U11^-1 (forward
+// substitution in the order of textbook elimination), written in place and
+// negated into negL (row r at negL + (r - J) * ldl + (j - J)).  Workgroup 0
+// also writes the factored block back.
+__global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(double* A, int64_t lda, int n,
+                                                               int j, int v, double* negL,
+                                                               int64_t ldl, int J) {
+  __shared__ double D[kLuMaxB][kLuMaxB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < v * v; e += kLuThreads)
+    D[e / v][e % v] = A[(int64_t)(j + e / v) * lda + j + e % v];
+  __syncthreads();
+  for (int c = 0; c < v; ++c) {
+    const double piv = D[c][c];
+    for (int r = c + 1 + tid; r < v; r += kLuThreads) D[r][c] = D[r][c] / piv;
+    __syncthreads();
+    const int w2 = v - c - 1;
+    for (int e = tid; e < w2 * w2; e += kLuThreads) {
+      const int r = c + 1 + e / w2, cc = c + 1 + e % w2;
+      D[r][cc] = D[r][cc] - D[r][c] * D[c][cc];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0)
+    for (int e = tid; e < v * v; e += kLuThreads)
+      A[(int64_t)(j + e / v) * lda + j + e % v] = D[e / v][e % v];
+  const int r = j + v + (int)blockIdx.x * kLuThreads + tid;
+  if (r >= n) return;
+  double x[kLuMaxB];
+  double* row = A + (int64_t)r * lda + j;
+#pragma unroll
+  for (int c = 0; c < kLuMaxB; ++c) x[c] = c < v ? row[c] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kLuMaxB; ++k) {
+    if (k < v) {
+      x[k] = x[k] / D[k][k];
+#pragma unroll
+      for (int c = k + 1; c < kLuMaxB; ++c)
+        if (c < v) x[c] = x[c] - x[k] * D[k][c];
+    }
+  }
+  double* nl = negL + (int64_t)(r - J) * ldl + (j - J);
+#pragma unroll
+  for (int c = 0; c < kLuMaxB; ++c)
+    if (c < v) {
+      row[c] = x[c];
+      nl[c] = -x[c];
+    }
+}
+
+// U12 = L11^-1 A12 for the columns [c0, c1) right of the factored v x v
+// block at (j, j): one column per thread (unit lower forward substitution,
+// in the order of textbook elimination), in place.
+__global__ __launch_bounds__(kLuThreads) void lu_row_solve_kernel(double* A, int64_t lda, int j,
+                                                                   int v, int c0, int c1) {
+  __shared__ double Lw[kLuMaxB][kLuMaxB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < v * v; e += kLuThreads)
+    Lw[e / v][e % v] = A[(int64_t)(j + e / v) * lda + j + e % v];
+  __syncthreads();
+  const int col = c0 + (int)blockIdx.x * kLuThreads + tid;
+  if (col >= c1) return;
+  double y[kLuMaxB];
+#pragma unroll
+  for (int r = 0; r < kLuMaxB; ++r) y[r] = r < v ? A[(int64_t)(j + r) * lda + col] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kLuMaxB; ++k) {
+    if (k < v) {
+#pragma unroll
+      for (int r = k + 1; r < kLuMaxB; ++r)
+        if (r < v) y[r] = y[r] - Lw[r][k] * y[k];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kLuMaxB; ++r)
+    if (r < v) A[(int64_t)(j + r) * lda + col] = y[r];
+}
+
+}  // namespace hs
+
+using hs::set_error;
+
+namespace {
+
+struct LuOuter {
+  int64_t J, w;
+  hsumma_plan_t trailing = nullptr;   // C = A[J+w:, J+w:], k = w (null when empty)
+};
+
+int lu_invalid(const std::string& msg) {
+  set_error(msg);
+  return HSUMMA_ERR_INVALID;
+}
+
+}  // namespace
+
+struct hsumma_lu_plan_s {
+  int64_t n = 0, b = 0, M = 0;
+  std::vector<LuOuter> outer;
+  size_t off_negL = 0, off_sub = 0, sub_bytes = 0, ws_bytes = 0;
+  ~hsumma_lu_plan_s() {
+    for (auto& o : outer)
+      if (o.trailing) hsumma_plan_destroy(o.trailing);
+  }
+};
+
+extern "C" {
+
+int hsumma_lu_plan(hsumma_lu_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, int64_t b,
+                   int64_t M, const hsumma_opts* opts) {
+  if (!out) return lu_invalid("null output pointer");
+  *out = nullptr;
+  if (n < 1 || n >= (int64_t(1) << 31)) return lu_invalid("n must be in [1, 2^31)");
+  if (b < 1 || b > hs::kLuMaxB) return lu_invalid("inner block b must be in [1, 64]");
+  if (M < b || M % b) return lu_invalid("outer block M must be a positive multiple of b");
+  if (P < 1 || Q < 1 || G < 1) return lu_invalid("P, Q and G must be >= 1");
+  hsumma_opts o;
+  hsumma_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.m || o.k) return lu_invalid("the LU factorisation is square: leave opts.m and opts.k 0");
+  hsumma_lu_plan_s* p = new (std::nothrow) hsumma_lu_plan_s();
+  if (!p) return lu_invalid("out of host memory");
+  p->n = n; p->b = b; p->M = M;
+  size_t sub = 256;
+  for (int64_t J = 0; J < n; J += M) {
+    LuOuter lo;
+    lo.J = J;
+    lo.w = std::min(M, n - J);
+    const int64_t rest = n - J - lo.w;
+    if (rest > 0) {
+      // the trailing update: a rest x rest block, k = w, on the P x Q grid
+      // (clamped to the block) with G groups where they can be arranged
+      hsumma_opts t = o;
+      t.m = rest;
+      t.k = lo.w;
+      const int32_t tp = (int32_t)std::min<int64_t>(P, rest), tq = (int32_t)std::min<int64_t>(Q, rest);
+      int I = 0, Jg = 0;
+      const int32_t tg = hs::factor_groups(tp, tq, G, &I, &Jg) ? G : 1;
+      const int64_t tb = std::min(b, lo.w);
+      const int64_t tM = (lo.w + tb - 1) / tb * tb;
+      int rc = hsumma_plan(&lo.trailing, rest, tp, tq, tg, tb, tM, &t);
+      if (rc) {
+        delete p;
+        return rc;
+      }
+      size_t need = 0;
+      hsumma_workspace_size(lo.trailing, &need);
+      sub = std::max(sub, need);
+    }
+    p->outer.push_back(lo);
+  }
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  p->off_negL = 0;
+  p->off_sub = al((size_t)n * (size_t)M * sizeof(double));
+  p->sub_bytes = al(sub);
+  p->ws_bytes = p->off_sub + p->sub_bytes;
+  *out = p;
+  return HSUMMA_OK;
+}
+
+void hsumma_lu_plan_destroy(hsumma_lu_plan_t p) { delete p; }
+
+int hsumma_lu_workspace_size(hsumma_lu_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return lu_invalid("null argument");
+  *bytes = p->ws_bytes;
+  return HSUMMA_OK;
+}
+
+int hsumma_lu(hsumma_lu_plan_t p, double* A, int64_t lda, void* ws, size_t ws_bytes,
+              void* stream) {
+  if (!p) return lu_invalid("null plan");
+  if (!A || (((uintptr_t)A) & 7)) return lu_invalid("A must be a non-null 8-byte-aligned pointer");
+  if (lda < p->n) return lu_invalid("lda smaller than n");
+  if (!ws || ws_bytes < p->ws_bytes) {
+    set_error("workspace missing or smaller than hsumma_lu_workspace_size()");
+    return HSUMMA_ERR_WORKSPACE;
+  }
+  if (((uintptr_t)ws) & 255) return lu_invalid("workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = p->n, M = p->M;
+  double* negL = (double*)((uint8_t*)ws + p->off_negL);
+  void* sub = (uint8_t*)ws + p->off_sub;
+  auto check = [&](hipError_t e, const char* what) {
+    if (e == hipSuccess) return HSUMMA_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
+  };
+  for (const LuOuter& o : p->outer) {
+    const int64_t J = o.J, w = o.w;
+    for (int64_t j = J; j < J + w; j += p->b) {
+      const int64_t v = std::min(p->b, J + w - j);
+      const int64_t below = n - j - v;
+      const int panel_wgs = (int)std::max<int64_t>(1, (below + hs::kLuThreads - 1) / hs::kLuThreads);
+      hipLaunchKernelGGL(hs::lu_panel_kernel, dim3(panel_wgs), dim3(hs::kLuThreads), 0, s, A,
+                         lda, (int)n, (int)j, (int)v, negL, (int64_t)M, (int)J);
+      int rc = check(hipGetLastError(), "LU panel launch");
+      if (rc) return rc;
+      const int64_t right = n - j - v;
+      if (right > 0) {
+        const int wgs = (int)((right + hs::kLuThreads - 1) / hs::kLuThreads);
+        hipLaunchKernelGGL(hs::lu_row_solve_kernel, dim3(wgs), dim3(hs::kLuThreads), 0, s, A,
+                           lda, (int)j, (int)v, (int)(j + v), (int)n);
+        if ((rc = check(hipGetLastError(), "LU row-solve launch"))) return rc;
+      }
+      // inside the outer panel: A[j+v:n, j+v:J+w] += (-L21) U12
+      const double* nl = negL + (j + v - J) * M + (j - J);
+      if (below > 0 && J + w - j - v > 0) {
+        rc = check(hs::launch_fp64_dense(nl, M, A + j * lda + (j + v), lda,
+                                         A + (j + v) * lda + (j + v), lda, below, J + w - j - v,
+                                         v, s),
+                   "LU panel update launch");
+        if (rc) return rc;
+      }
+      // the outer panel's rows right of it: A[j+v:J+w, J+w:n] += (-L) U12
+      if (J + w - j - v > 0 && n - J - w > 0) {
+        rc = check(hs::launch_fp64_dense(nl, M, A + j * lda + (J + w), lda,
+                                         A + (j + v) * lda + (J + w), lda, J + w - j - v,
+                                         n - J - w, v, s),
+                   "LU row-block update launch");
+        if (rc) return rc;
+      }
+    }
+    // the trailing matrix: one HSUMMA outer update with k = w
+    if (o.trailing) {
+      int rc = hsumma_outer_update(o.trailing, 0, negL + w * M, M, A + J * lda + (J + w), lda,
+                                   A + (J + w) * lda + (J + w), lda, sub, p->sub_bytes, stream);
+      if (rc) return rc;
+    }
+  }
+  return HSUMMA_OK;
+}
+
+}  // extern "C"

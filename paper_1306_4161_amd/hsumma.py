@@ -23,7 +23,8 @@ EXPORTED = [
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
     "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
     "hsumma_work_items", "hsumma_prepare_workspace", "hsumma_run_noalloc",
-    "hsumma_noalloc_max_workspace",
+    "hsumma_noalloc_max_workspace", "hsumma_lu_plan", "hsumma_lu_workspace_size", "hsumma_lu",
+    "hsumma_lu_plan_destroy",
     "hsumma_mlp_param_count", "hsumma_mlp_work_floats", "hsumma_mlp_forward", "hsumma_mlp_grad",
     "hsumma_mlp_adam", "hsumma_model_bcast", "hsumma_model_cost", "hsumma_model_dcomm_dgroups",
     "hsumma_model_select_groups", "hsumma_model_cost_levels",
@@ -103,6 +104,11 @@ def lib():
         L.hsumma_prepare_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.hsumma_run_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp]
         L.hsumma_noalloc_max_workspace.argtypes = []
+        L.hsumma_lu_plan.argtypes = [P(vp), i64, i32, i32, i32, i64, i64, P(Opts)]
+        L.hsumma_lu_workspace_size.argtypes = [vp, P(ctypes.c_size_t)]
+        L.hsumma_lu.argtypes = [vp, vp, i64, vp, ctypes.c_size_t, vp]
+        L.hsumma_lu_plan_destroy.argtypes = [vp]
+        L.hsumma_lu_plan_destroy.restype = None
         L.hsumma_panel_slices.argtypes = [vp, vp, P(i32), vp]
         sz = ctypes.c_size_t
         L.hsumma_split_layout.argtypes = [vp, P(sz), P(sz), P(sz), P(sz), P(i32), P(i32)]
@@ -127,7 +133,7 @@ def lib():
         L.hsumma_version.argtypes = []
         for name in EXPORTED:
             if name not in ("hsumma_opts_default", "hsumma_plan_destroy",
-                            "hsumma_last_error", "hsumma_version"):
+                            "hsumma_lu_plan_destroy", "hsumma_last_error", "hsumma_version"):
                 getattr(L, name).restype = ctypes.c_int
         L.hsumma_noalloc_max_workspace.restype = ctypes.c_size_t
         L.hsumma_mlp_param_count.restype = i64
@@ -308,6 +314,52 @@ class Plan:
                                          ctypes.byref(w), ctypes.byref(np_)))
         return dict(off_digA=v[0].value, off_digB=v[1].value, off_eA=v[2].value,
                     off_fB=v[3].value, Wp=w.value, planes=np_.value)
+
+
+class LuPlan:
+    """LU factorisation without pivoting whose trailing update is the HSUMMA
+    local update (see hsumma_lu in include/hsumma.h)."""
+
+    def __init__(self, n, P, Q, G, b, M, *, prec=FP64, **kw):
+        L = lib()
+        o = Opts()
+        L.hsumma_opts_default(ctypes.byref(o))
+        o.prec = prec
+        for key, val in kw.items():
+            setattr(o, key, val)
+        h = ctypes.c_void_p()
+        _check(L.hsumma_lu_plan(ctypes.byref(h), n, P, Q, G, b, M, ctypes.byref(o)))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hsumma_lu_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_size(self):
+        v = ctypes.c_size_t()
+        _check(lib().hsumma_lu_workspace_size(self._h, ctypes.byref(v)))
+        return v.value
+
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_size, dtype=torch.uint8, device=device)
+
+    def factor(self, A, ws, stream=None):
+        """A = L U in place (A: n x n float64 CUDA tensor, row-major)."""
+        a, lda = _dev_ptr(A, "A")
+        if tuple(A.shape) != (self.n, self.n):
+            raise ValueError("A must be n x n")
+        _check(lib().hsumma_lu(self._h, a, lda, ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def mfma_exact_probe(fmt, a_digits, b_digits, stream=None):

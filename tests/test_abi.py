@@ -249,3 +249,23 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch_array():
     assert L.hsumma_run_noalloc(big._h, A, 16384, B, 16384, C, 16384, None) == hs.ERR_WORKSPACE
     assert "scratch" in L.hsumma_last_error().decode()
     big.close()
+
+
+def test_lu_plans_validate_and_size_their_workspace():
+    with pytest.raises(hs.HsummaError):
+        hs.LuPlan(256, 1, 1, 1, 128, 128)            # b beyond the 64 of the panel kernels
+    with pytest.raises(hs.HsummaError):
+        hs.LuPlan(256, 1, 1, 1, 32, 48)              # M not a multiple of b
+    with pytest.raises(hs.HsummaError):
+        hs.LuPlan(256, 1, 1, 1, 32, 16)              # M < b
+    p = hs.LuPlan(1000, 4, 4, 16, 64, 256)
+    # the negated L21 panel (n x M doubles) plus the trailing updates' workspace
+    assert p.workspace_size >= 1000 * 256 * 8 + 16 * ((1000 - 256 + 127) // 128) ** 2
+    q = hs.LuPlan(1000, 4, 4, 16, 64, 256, prec=hs.SPLIT_INT8)
+    assert q.workspace_size > p.workspace_size       # digit planes of the trailing updates
+    import ctypes
+    ws = ctypes.c_void_p(0x7000000)
+    A = ctypes.c_void_p(0x100000)
+    assert hs.lib().hsumma_lu(p._h, A, 1000, ws, p.workspace_size - 1, None) == hs.ERR_WORKSPACE
+    assert hs.lib().hsumma_lu(p._h, A, 999, ws, p.workspace_size, None) == hs.ERR_INVALID
+    p.close(); q.close()
