@@ -7,10 +7,9 @@
 // M columns, each factored in inner blocks of b columns.  For outer panel
 // [J, J + w) and each inner block [j, j + v) of it:
 //   1. factor the v x v diagonal block (textbook elimination) and solve
-//      L21 = A21 U11^-1 for every row below it (lu_panel_kernel); -L21 is
-//      also written to the workspace, so the updates below are C += A B;
-//   2. U12 = L11^-1 A12 for every column right of the block
-//      (lu_row_solve_kernel);
+//      L21 = A21 U11^-1 for every row below it; -L21 is also written to the
+//      workspace, so the updates below are C += A B;
+//   2. U12 = L11^-1 A12 for every column right of the block;
 //   3. the update inside the outer panel, A[j+v:, j+v:J+w] -= L21 U12, and
 //      on the outer panel's own rows right of it, A[j+v:J+w, J+w:] -= L U12
 //      (dense FP64 updates, k = v).
@@ -24,6 +23,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -110,6 +110,118 @@ __global__ __launch_bounds__(kLuThreads) void lu_row_solve_kernel(double* A, int
 #pragma unroll
   for (int r = 0; r < kLuMaxB; ++r)
     if (r < v) A[(int64_t)(j + r) * lda + col] = y[r];
+}
+
+// ---- full blocks of a compile-time width V (no per-element guards) ---------
+// One wave factors the V x V diagonal block: lane t holds row t; at step c
+// lane c publishes its (final) row through LDS and every lane below it
+// eliminates with it.  The block is written back in place.
+template <int V>
+__global__ __launch_bounds__(64) void lu_diag_kernel(double* A, int64_t lda, int j) {
+  __shared__ double prow[V];
+  const int t = threadIdx.x;
+  double x[V];
+  double* row = A + (int64_t)(j + min(t, V - 1)) * lda + j;
+#pragma unroll
+  for (int c = 0; c < V; ++c) x[c] = row[c];
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    if (t == c) {
+#pragma unroll
+      for (int cc = c; cc < V; ++cc) prow[cc] = x[cc];
+    }
+    __syncthreads();
+    if (t > c && t < V) {
+      x[c] = x[c] / prow[c];
+#pragma unroll
+      for (int cc = c + 1; cc < V; ++cc) x[cc] = x[cc] - x[c] * prow[cc];
+    }
+    __syncthreads();
+  }
+  if (t < V) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) row[c] = x[c];
+  }
+}
+
+// L21 = A21 U11^-1 for the rows j + V + 64 * blockIdx.x + lane (U11 read from
+// the factored block), in place and negated into negL.
+template <int V>
+__global__ __launch_bounds__(64) void lu_l21_kernel(double* A, int64_t lda, int n, int j,
+                                                     double* negL, int64_t ldl, int J) {
+  __shared__ double U[V][V + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < V * V; e += 64) U[e / V][e % V] = A[(int64_t)(j + e / V) * lda + j + e % V];
+  __syncthreads();
+  const int r = j + V + (int)blockIdx.x * 64 + t;
+  if (r >= n) return;
+  double x[V];
+  double* row = A + (int64_t)r * lda + j;
+#pragma unroll
+  for (int c = 0; c < V; ++c) x[c] = row[c];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    x[k] = x[k] / U[k][k];
+#pragma unroll
+    for (int c = k + 1; c < V; ++c) x[c] = x[c] - x[k] * U[k][c];
+  }
+  double* nl = negL + (int64_t)(r - J) * ldl + (j - J);
+#pragma unroll
+  for (int c = 0; c < V; ++c) {
+    row[c] = x[c];
+    nl[c] = -x[c];
+  }
+}
+
+// U12 = L11^-1 A12 for the columns [c0, c1): one column per lane; L11 is kept
+// transposed in LDS so that the multipliers of one step are contiguous.
+template <int V>
+__global__ __launch_bounds__(64) void lu_u12_kernel(double* A, int64_t lda, int j, int c0,
+                                                     int c1) {
+  __shared__ double Lt[V][V + 2];
+  const int t = threadIdx.x;
+  for (int e = t; e < V * V; e += 64) Lt[e % V][e / V] = A[(int64_t)(j + e / V) * lda + j + e % V];
+  __syncthreads();
+  const int col = c0 + (int)blockIdx.x * 64 + t;
+  if (col >= c1) return;
+  double y[V];
+#pragma unroll
+  for (int r = 0; r < V; ++r) y[r] = A[(int64_t)(j + r) * lda + col];
+#pragma unroll
+  for (int k = 0; k < V; ++k)
+#pragma unroll
+    for (int r = k + 1; r < V; ++r) y[r] = y[r] - Lt[k][r] * y[k];
+#pragma unroll
+  for (int r = 0; r < V; ++r) A[(int64_t)(j + r) * lda + col] = y[r];
+}
+
+// The panel steps of one inner block [j, j + v): the fast kernels when v is
+// 16, 32 or 64, else the general ones above.
+hipError_t lu_panel_step(double* A, int64_t lda, int n, int j, int v, double* negL, int64_t ldl,
+                         int J, hipStream_t s) {
+  const int below = n - j - v, right = n - j - v;
+  auto fast = [&](auto vc) {
+    constexpr int V = decltype(vc)::value;
+    hipLaunchKernelGGL(lu_diag_kernel<V>, dim3(1), dim3(64), 0, s, A, lda, j);
+    if (below > 0)
+      hipLaunchKernelGGL(lu_l21_kernel<V>, dim3((below + 63) / 64), dim3(64), 0, s, A, lda, n, j,
+                         negL, ldl, J);
+    if (right > 0)
+      hipLaunchKernelGGL(lu_u12_kernel<V>, dim3((right + 63) / 64), dim3(64), 0, s, A, lda, j,
+                         j + v, n);
+  };
+  if (v == 64) fast(std::integral_constant<int, 64>{});
+  else if (v == 32) fast(std::integral_constant<int, 32>{});
+  else if (v == 16) fast(std::integral_constant<int, 16>{});
+  else {
+    const int wgs = std::max(1, (below + kLuThreads - 1) / kLuThreads);
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(wgs), dim3(kLuThreads), 0, s, A, lda, n, j, v, negL,
+                       ldl, J);
+    if (right > 0)
+      hipLaunchKernelGGL(lu_row_solve_kernel, dim3((right + kLuThreads - 1) / kLuThreads),
+                         dim3(kLuThreads), 0, s, A, lda, j, v, j + v, n);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace hs
@@ -226,18 +338,9 @@ int hsumma_lu(hsumma_lu_plan_t p, double* A, int64_t lda, void* ws, size_t ws_by
     for (int64_t j = J; j < J + w; j += p->b) {
       const int64_t v = std::min(p->b, J + w - j);
       const int64_t below = n - j - v;
-      const int panel_wgs = (int)std::max<int64_t>(1, (below + hs::kLuThreads - 1) / hs::kLuThreads);
-      hipLaunchKernelGGL(hs::lu_panel_kernel, dim3(panel_wgs), dim3(hs::kLuThreads), 0, s, A,
-                         lda, (int)n, (int)j, (int)v, negL, (int64_t)M, (int)J);
-      int rc = check(hipGetLastError(), "LU panel launch");
+      int rc = check(hs::lu_panel_step(A, lda, (int)n, (int)j, (int)v, negL, M, (int)J, s),
+                     "LU panel launch");
       if (rc) return rc;
-      const int64_t right = n - j - v;
-      if (right > 0) {
-        const int wgs = (int)((right + hs::kLuThreads - 1) / hs::kLuThreads);
-        hipLaunchKernelGGL(hs::lu_row_solve_kernel, dim3(wgs), dim3(hs::kLuThreads), 0, s, A,
-                           lda, (int)j, (int)v, (int)(j + v), (int)n);
-        if ((rc = check(hipGetLastError(), "LU row-solve launch"))) return rc;
-      }
       // inside the outer panel: A[j+v:n, j+v:J+w] += (-L21) U12
       const double* nl = negL + (j + v - J) * M + (j - J);
       if (below > 0 && J + w - j - v > 0) {

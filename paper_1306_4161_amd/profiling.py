@@ -13,6 +13,8 @@ the text summaries made from rocprofv3's CSV output.
     python3 -m paper_1306_4161_amd.profiling mfma OUT/m_counter_collection.csv --kernel fp64_dma_kernel ...
     # per-kernel time table from `rocprofv3 --kernel-trace --stats`
     python3 -m paper_1306_4161_amd.profiling stats OUT/kt_kernel_stats.csv --command "..."
+    # the same over the steady state (first dispatches of each kernel left out)
+    python3 -m paper_1306_4161_amd.profiling trace OUT/kt_kernel_trace.csv --skip 3 --command "..."
 
 FETCH_SIZE and WRITE_SIZE count L2-to-memory traffic in KiB per dispatch.
 Each is scaled by what it reads for a plain copy of known size (bytes copied
@@ -201,6 +203,51 @@ def stats(args):
     print(text, end="")
 
 
+def trace(args):
+    """Per-kernel time from a --kernel-trace CSV over the steady state: after
+    every idle gap of the GPU longer than `gap_ms` (host work between timed
+    regions, during which the clocks drop) the first `skip` dispatches of
+    each kernel are left out."""
+    disp = []
+    with open(args.csv) as f:
+        for r in csv.DictReader(f):
+            disp.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    disp.sort()
+    per = collections.defaultdict(list)
+    calls = collections.Counter()
+    since_gap = collections.Counter()
+    last_end = None
+    for st, en, name in disp:
+        if last_end is not None and st - last_end > args.gap_ms * 1e6:
+            since_gap.clear()
+        last_end = en if last_end is None else max(last_end, en)
+        calls[name] += 1
+        since_gap[name] += 1
+        if since_gap[name] > args.skip:
+            per[name].append((en - st) / 1e3)
+    rows = []
+    for name in calls:
+        durs = per.get(name) or []
+        if durs:
+            rows.append((sum(durs), name, calls[name], len(durs), durs))
+    rows.sort(reverse=True)
+    lines = ["# per-kernel time, steady state: after every idle gap over %g ms the first "
+             "%d dispatches of each kernel are left out" % (args.gap_ms, args.skip),
+             "# command: %s" % args.command,
+             "# summary command: python3 -m paper_1306_4161_amd.profiling %s" % shlex.join(
+                 sys.argv[1:]),
+             "%-64s %6s %6s %11s %11s %11s %11s" % ("kernel", "calls", "kept", "avg_us",
+                                                      "min_us", "max_us", "total_ms")]
+    for total, name, calls, kept, durs in rows[: args.top]:
+        lines.append("%-64s %6d %6d %11.1f %11.1f %11.1f %11.3f" % (
+            name[:64], calls, kept, total / kept, min(durs), max(durs), total / 1e3))
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -238,8 +285,16 @@ def main():
     s.add_argument("--command", default="")
     s.add_argument("--top", type=int, default=12)
     s.add_argument("--out", default="")
+    tr = sub.add_parser("trace")
+    tr.add_argument("csv")
+    tr.add_argument("--skip", type=int, default=3)
+    tr.add_argument("--gap-ms", type=float, default=20.0)
+    tr.add_argument("--command", default="")
+    tr.add_argument("--top", type=int, default=12)
+    tr.add_argument("--out", default="")
     args = ap.parse_args()
-    {"launches": launches, "traffic": traffic, "mfma": mfma, "stats": stats}[args.cmd](args)
+    {"launches": launches, "traffic": traffic, "mfma": mfma, "stats": stats,
+     "trace": trace}[args.cmd](args)
 
 
 if __name__ == "__main__":
