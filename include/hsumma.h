@@ -109,7 +109,9 @@ typedef struct {
                       /* 0 => 48 (50 for INT8)                                  */
   int32_t staged;     /* FP64 path: 1 = always the register-staged kernel,      */
                       /* 0 = direct-to-LDS loads where alignment allows         */
-  int32_t reserved[4];
+  int32_t waves;      /* FP64 path: waves per workgroup of the macro-tile's     */
+                      /* kernel; 0 => the tile's first compiled configuration   */
+  int32_t reserved[3];
 } hsumma_opts;
 
 /* Fill *o with defaults (all zero: square, block, FP64, default tiles). */

@@ -34,7 +34,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# HSUMMA_ORACLE_SANITIZE=1: the AddressSanitizer / UndefinedBehaviorSanitizer
+# build (liboracle_asan.so; the process must preload gcc's libasan)
+_SANITIZE = os.environ.get("HSUMMA_ORACLE_SANITIZE") == "1"
+_LIB_PATH = os.environ.get("HSUMMA_ORACLE_LIBRARY") or os.path.join(
+    _HERE, "liboracle_asan.so" if _SANITIZE else "liboracle.so")
 _lib = None
 
 U = 2.0 ** -53  # unit roundoff of binary64
@@ -45,11 +49,15 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH) or (
         os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
     ):
+        os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = [
             "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
             "-shared", "-fPIC", "-o", tmp, _SRC, "-lm",
         ]
+        if _SANITIZE:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

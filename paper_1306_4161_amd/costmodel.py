@@ -1,10 +1,15 @@
 """Learned cost model: an MLP that predicts the best kernel configuration.
 
 Trained on the autotuner's own timings (tune.py).  Input: features of one
-problem shape (sizes, grid, groups, outer block, value spread).  Output: the
-predicted log2 run time of every candidate configuration; the prediction
-picks the allowed candidate with the smallest one, so a new shape needs one
-forward pass instead of an exhaustive search.  Exhaustive search stays the
+problem shape (sizes, grid, groups, outer block, value spread, work items
+per macro-tile width).  Output: the predicted log2 run time of every
+candidate configuration relative to the shape's mean; a new shape needs one
+forward pass instead of an exhaustive search.  The pick is the single
+configuration best on the training shapes unless the network predicts
+another one faster by more than a margin, chosen on a validation fifth of
+the training shapes (timing noise of a few per cent on short launches
+exceeds many of the real differences, and an argmin over noisy predictions
+picks needlessly away from a good default).  Exhaustive search stays the
 fallback and the yardstick: regret = t(picked) / t(best) - 1.
 
 Training and inference run in the library's own HIP kernels
@@ -30,20 +35,30 @@ HIDDEN = 64
 
 
 def features(shape) -> np.ndarray:
-    """Feature vector of a shape (dict or tune.Shape)."""
+    """Feature vector of a shape (dict or tune.Shape): sizes, grid, groups,
+    outer block, value spread, and for each macro-tile width t the number of
+    work items of a t x t tiling and the fraction of their area that is
+    inside C (ragged tiles waste the rest)."""
     s = shape if isinstance(shape, dict) else shape.__dict__
     m, n, k, P, Q, G, M = (float(s[x]) for x in ("m", "n", "k", "P", "Q", "G", "M"))
     l2 = math.log2
+    tiles = []
+    for t in (32, 64, 128, 256):
+        items = P * Q * math.ceil(m / P / t) * math.ceil(n / Q / t)
+        tiles += [l2(items), m * n / (items * t * t)]
     return np.array([
         l2(m), l2(n), l2(k), l2(M), l2(P), l2(Q), l2(G),
         l2(m / P), l2(n / Q), l2(m * n * M) / 3.0,
         s.get("sigma", 0.0), float(s.get("sigma", 0.0) > tune.SPLIT_MAX_SIGMA),
         l2(m / P) - l2(n / Q), (m / P) % 128 / 128.0, (n / Q) % 128 / 128.0,
-    ], dtype=np.float64)
+    ] + tiles, dtype=np.float64)
 
 
 def targets(rows):
-    """(T, mask): log2 ms per candidate, 1 where timed."""
+    """(T, mask): log2 ms per candidate relative to the shape's mean over its
+    timed candidates (the ranking is what the pick needs; the common scale
+    of a shape would otherwise take most of the network's fit), 1 where
+    timed."""
     K = len(tune.NAMES)
     T = np.zeros((len(rows), K))
     mask = np.zeros((len(rows), K))
@@ -52,6 +67,8 @@ def targets(rows):
             if name in r["times"]:
                 T[i, j] = math.log2(max(r["times"][name], 1e-4))
                 mask[i, j] = 1.0
+        if mask[i].any():
+            T[i] = np.where(mask[i] > 0, T[i] - T[i][mask[i] > 0].mean(), 0.0)
     return T, mask
 
 
@@ -105,14 +122,22 @@ class CostModel:
         Z = hs.mlp_forward(self._x(X), self.params, HIDDEN, self.K)
         return Z.cpu().numpy().astype(np.float64) + self.tmu
 
-    def choose(self, X, shapes) -> list:
+    def choose(self, X, shapes, fallback: str | None = None, margin: float = 0.0) -> list:
+        """The candidate with the smallest predicted time; with a fallback,
+        that one unless the pick is predicted faster by more than `margin`
+        (log2 units)."""
         Z = self.predict(X)
         out = []
         for i, sh in enumerate(shapes):
             s = sh if isinstance(sh, dict) else sh.__dict__
             shp = tune.Shape(**s)
             order = np.argsort(Z[i])
-            out.append(next(tune.NAMES[j] for j in order if tune.allowed(shp, tune.NAMES[j])))
+            pick = next(tune.NAMES[j] for j in order if tune.allowed(shp, tune.NAMES[j]))
+            if fallback is not None:
+                jf, jp = tune.NAMES.index(fallback), tune.NAMES.index(pick)
+                if Z[i, jf] - Z[i, jp] <= margin:
+                    pick = fallback
+            out.append(pick)
         return out
 
 
@@ -132,30 +157,47 @@ def summarize(rg: np.ndarray) -> dict:
 
 
 def experiment(n_shapes: int, seed: int, n_test: int = 200, epochs: int = 2000, log=print,
-               lo: int = 512, hi: int = 16384):
+               lo: int = 512, hi: int = 16384, reps: int = 3):
     """Dataset -> train on n_shapes - n_test -> regret on the held-out shapes."""
     shapes = tune.random_shapes(n_shapes, seed, lo=lo, hi=hi)
     t0 = time.time()
-    rows = tune.build_dataset(shapes, log=log)
+    rows = tune.build_dataset(shapes, reps=reps, log=log)
     t_label = time.time() - t0
     X = np.stack([features(r["shape"]) for r in rows])
     T, mask = targets(rows)
     ntr = n_shapes - n_test
+    # the training shapes: 80 % fit the network, 20 % choose the margin by
+    # which a predicted gain must beat the best static configuration
+    nfit = max(1, int(0.8 * ntr))
+    best_static = min(tune.NAMES, key=lambda nm: np.mean(regret(rows[:nfit], [nm] * nfit)))
     model = CostModel(X.shape[1], T.shape[1], seed=seed)
-    hist = model.fit(X[:ntr], T[:ntr], mask[:ntr], epochs=epochs, log=log)
+    hist = model.fit(X[:nfit], T[:nfit], mask[:nfit], epochs=epochs, log=log)
+    val_rows = rows[nfit:ntr]
+    margins = [0.0, 0.05, 0.1, 0.2, 0.3, 0.5, 0.75, 1.0, 1e9]
+    val = {mg: float(np.mean(regret(val_rows, model.choose(X[nfit:ntr], [r["shape"] for r in val_rows],
+                                                          best_static, mg))))
+           for mg in margins} if val_rows else {1e9: 0.0}
+    margin = min(val, key=lambda mg: (val[mg], -mg))
     test_rows = rows[ntr:]
     t1 = time.time()
-    picks = model.choose(X[ntr:], [r["shape"] for r in test_rows])
+    picks = model.choose(X[ntr:], [r["shape"] for r in test_rows], best_static, margin)
     t_pred = time.time() - t1
     rg_mlp = regret(test_rows, picks)
+    rg_argmin = regret(test_rows, model.choose(X[ntr:], [r["shape"] for r in test_rows]))
+    # baselines: the library's own untuned choice (size-aware), the fixed
+    # large-shape default, and the single configuration best on the
+    # training shapes
+    rg_lib = regret(test_rows, [tune.library_default(r["shape"]) for r in test_rows])
     rg_def = regret(test_rows, [tune.DEFAULT] * len(test_rows))
-    best_static = min(tune.NAMES, key=lambda nm: np.mean(regret(rows[:ntr], [nm] * ntr)))
     rg_static = regret(test_rows, [best_static] * len(test_rows))
     exhaustive_ms = float(np.mean([sum(r["times"].values()) for r in test_rows]))
     return {
         "shapes": n_shapes, "train": ntr, "test": n_test, "seed": seed,
         "labeling_seconds": t_label, "loss_history": hist,
-        "regret_mlp": summarize(rg_mlp), "regret_default": summarize(rg_def),
+        "regret_mlp": summarize(rg_mlp), "regret_mlp_argmin": summarize(rg_argmin),
+        "margin_log2": margin, "validation_regret_by_margin": val,
+        "regret_library_default": summarize(rg_lib),
+        "regret_fixed_default": summarize(rg_def),
         "regret_best_static": summarize(rg_static), "best_static": best_static,
         "prediction_seconds_per_shape": t_pred / max(1, n_test),
         "exhaustive_timed_ms_per_shape": exhaustive_ms,

@@ -529,14 +529,19 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
 
   // Tile configuration.
   if (o.prec == HSUMMA_FP64) {
-    hs::TileCfg cfg{o.tile_m ? o.tile_m : 128, o.tile_n ? o.tile_n : 128, o.kc ? o.kc : 16};
-    if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) cfg = {64, 64, 16};
+    hs::TileCfg cfg{o.tile_m ? o.tile_m : 128, o.tile_n ? o.tile_n : 128, o.kc ? o.kc : 16,
+                    o.waves};
+    if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) cfg = {64, 64, 16, o.waves};
     bool ok = false;
     for (auto& c : hs::fp64_configs())
-      if (c.tm == cfg.tm && c.tn == cfg.tn && c.kc == cfg.kc) ok = true;
+      if (hs::same_tile(cfg, c)) {
+        ok = true;
+        cfg.waves = c.waves;           // the first compiled configuration of the tile
+        break;
+      }
     if (!ok) {
       delete p;
-      return invalid("tile configuration (tile_m, tile_n, kc) not compiled into the library");
+      return invalid("tile configuration (tile_m, tile_n, kc, waves) not compiled into the library");
     }
     p->cfg = cfg;
   } else {
@@ -544,7 +549,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     // every form: 64 x 128 macro-tiles streamed in 16-k steps (32-k for INT8)
     const hs::TileCfg scfg{64, 128, p->fmt == 2 ? 32 : 16};
     if ((o.tile_m && o.tile_m != scfg.tm) || (o.tile_n && o.tile_n != scfg.tn) ||
-        (o.kc && o.kc != scfg.kc)) {
+        (o.kc && o.kc != scfg.kc) || (o.waves && o.waves != 4)) {
       delete p;
       return invalid("split forms use fixed 64 x 128 macro-tiles and 16-k steps (32-k for INT8)");
     }

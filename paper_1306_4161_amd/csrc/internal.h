@@ -69,8 +69,16 @@ __device__ __forceinline__ void ring_barrier() {
 // format 32 bits, no swizzle, no index stride.
 constexpr int kBufferWord3 = 0x00020000;
 
-// Kernel configurations (macro-tile and k-chunk) compiled into the library.
-struct TileCfg { int tm, tn, kc; };
+// Kernel configurations (macro-tile, k-chunk, waves per workgroup) compiled
+// into the library; waves = 0 selects the first configuration of that tile.
+struct TileCfg {
+  int tm, tn, kc;
+  int waves = 0;
+};
+inline bool same_tile(const TileCfg& want, const TileCfg& have) {
+  return want.tm == have.tm && want.tn == have.tn && want.kc == have.kc &&
+         (want.waves == 0 || want.waves == have.waves);
+}
 const std::vector<TileCfg>& fp64_configs();
 // dma: use the direct-to-LDS kernel of this configuration if there is one
 // (the caller guarantees 16-byte granularity of every k-range and column run)

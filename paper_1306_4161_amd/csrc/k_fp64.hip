@@ -439,8 +439,9 @@ struct Fp64Entry {
   int occupancy;
 };
 
-#define HS_FP64(TM, TN, KC, WM, WN, OCC) \
-  Fp64Entry{TileCfg{TM, TN, KC}, fp64_update_kernel<TM, TN, KC, WM, WN, OCC>, WM * WN * 64, OCC}
+#define HS_FP64(TM, TN, KC, WM, WN, OCC)                                                 \
+  Fp64Entry{TileCfg{TM, TN, KC, WM * WN}, fp64_update_kernel<TM, TN, KC, WM, WN, OCC>,    \
+            WM * WN * 64, OCC}
 
 const std::vector<Fp64Entry>& table() {
   static const std::vector<Fp64Entry> t = {
@@ -455,6 +456,12 @@ const std::vector<Fp64Entry>& table() {
       HS_FP64(64, 64, 16, 2, 2, 4),
       HS_FP64(64, 64, 32, 2, 2, 2),
       HS_FP64(32, 32, 16, 2, 2, 8),
+      // wider tiles and another wave count (tuner candidates).  No 256 x 256:
+      // its FP64 accumulators alone (512 KB) are a CU's whole register file.
+      HS_FP64(128, 256, 16, 2, 4, 1),
+      HS_FP64(64, 256, 16, 1, 4, 1),
+      HS_FP64(256, 64, 16, 4, 1, 1),
+      HS_FP64(128, 128, 16, 4, 2, 1),
   };
   return t;
 }
@@ -465,8 +472,9 @@ struct DmaEntry {
   int threads;
   int occupancy;
 };
-#define HS_DMA(TM, TN, NS, WM, WN, OCC) \
-  DmaEntry{TileCfg{TM, TN, 16}, fp64_dma_kernel<TM, TN, NS, WM, WN, OCC>, WM * WN * 64, OCC}
+#define HS_DMA(TM, TN, NS, WM, WN, OCC)                                                  \
+  DmaEntry{TileCfg{TM, TN, 16, WM * WN}, fp64_dma_kernel<TM, TN, NS, WM, WN, OCC>,        \
+           WM * WN * 64, OCC}
 // direct-to-LDS kernels, keyed by the staged kernel configuration they replace
 const std::vector<DmaEntry>& dma_table() {
   static const std::vector<DmaEntry> t = {
@@ -475,6 +483,10 @@ const std::vector<DmaEntry>& dma_table() {
       HS_DMA(64, 64, 4, 2, 2, 2),
       HS_DMA(128, 64, 3, 2, 2, 2),
       HS_DMA(64, 128, 3, 2, 2, 2),
+      HS_DMA(128, 256, 2, 2, 4, 1),
+      HS_DMA(64, 256, 3, 1, 4, 1),
+      HS_DMA(256, 64, 3, 4, 1, 1),
+      HS_DMA(128, 128, 3, 4, 2, 1),
   };
   return t;
 }
@@ -491,13 +503,13 @@ const std::vector<TileCfg>& fp64_configs() {
 
 int fp64_occupancy(const TileCfg& cfg) {
   for (auto& e : table())
-    if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) return e.occupancy;
+    if (same_tile(cfg, e.cfg)) return e.occupancy;
   return 0;
 }
 
 bool fp64_has_dma(const TileCfg& cfg) {
   for (auto& e : dma_table())
-    if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) return true;
+    if (same_tile(cfg, e.cfg)) return true;
   return false;
 }
 
@@ -525,14 +537,14 @@ hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStr
                        bool dma) {
   if (dma) {
     for (auto& e : dma_table()) {
-      if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) {
+      if (same_tile(cfg, e.cfg)) {
         hipLaunchKernelGGL(e.kern, dim3(grid), dim3(e.threads), 0, s, a);
         return hipGetLastError();
       }
     }
   }
   for (auto& e : table()) {
-    if (e.cfg.tm == cfg.tm && e.cfg.tn == cfg.tn && e.cfg.kc == cfg.kc) {
+    if (same_tile(cfg, e.cfg)) {
       hipLaunchKernelGGL(e.kern, dim3(grid), dim3(e.threads), 0, s, a);
       return hipGetLastError();
     }

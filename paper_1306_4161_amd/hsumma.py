@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhsumma.so")
+# HSUMMA_LIBRARY selects another build of the library (e.g. the host-sanitized
+# libhsumma_asan.so of `python -m paper_1306_4161_amd.build --sanitize`)
+LIB_PATH = os.environ.get("HSUMMA_LIBRARY") or os.path.join(HERE, "libhsumma.so")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_WORKSPACE = 0, -1, -2, -3, -4
 FP64, SPLIT_BF16, SPLIT_FP8, SPLIT_INT8 = 0, 1, 2, 3
@@ -54,8 +56,8 @@ class Opts(ctypes.Structure):
         ("slices", ctypes.c_int32), ("min_slices", ctypes.c_int32), ("max_slices", ctypes.c_int32),
         ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32), ("kc", ctypes.c_int32),
         ("persistent", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-        ("tau_bits", ctypes.c_int32), ("staged", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("tau_bits", ctypes.c_int32), ("staged", ctypes.c_int32), ("waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -172,7 +174,7 @@ class Plan:
 
     def __init__(self, n, P, Q, G, b, M=None, *, m=0, k=0, dist=DIST_BLOCK, nb=0,
                  prec=FP64, slices=0, min_slices=0, max_slices=0, tile_m=0, tile_n=0,
-                 kc=0, persistent=0, use_graph=0, tau_bits=0, staged=0):
+                 kc=0, persistent=0, use_graph=0, tau_bits=0, staged=0, waves=0):
         L = lib()
         o = Opts()
         L.hsumma_opts_default(ctypes.byref(o))
@@ -180,6 +182,7 @@ class Plan:
         o.slices, o.min_slices, o.max_slices = slices, min_slices, max_slices
         o.tile_m, o.tile_n, o.kc = tile_m, tile_n, kc
         o.persistent, o.use_graph, o.tau_bits, o.staged = persistent, use_graph, tau_bits, staged
+        o.waves = waves
         h = ctypes.c_void_p()
         _check(L.hsumma_plan(ctypes.byref(h), n, P, Q, G, b, M if M is not None else b,
                              ctypes.byref(o)))

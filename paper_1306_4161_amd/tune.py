@@ -3,13 +3,17 @@
 The paper picks its number of groups G by sampling a few HSUMMA iterations
 with different values (Sec. V-A's model validation, Sec. VI).  On one GPU the
 knobs that change speed but not the product are the kernel configuration of
-the local update: the macro-tile and k-chunk of the FP64 path, the grouped
-persistent launch, and the precision form.  The tuner times one outer step
+the local update: the macro-tile, k-chunk and waves per workgroup of the
+FP64 path, the grouped persistent launch, and the precision form (the split
+forms with their per-panel slice count, which the library chooses to meet
+the FP64 accuracy target and replaces by the FP64 kernel on panels it cannot
+carry, so every candidate is FP64-accurate).  The tuner times one outer step
 (hsumma_outer_update: every inner step of one outer block, one launch) of
 each candidate -- per-step cost is uniform over the steps -- and keeps the
-fastest one that is allowed for the shape: the BF16 split form only where
-its accuracy on the shape's value distribution is established (exponent
-spread sigma <= 2, see tests/test_parity_split.py).
+fastest.  The inner block b does not enter: within an outer update the
+kernels only restart their 4-deep MFMA k-groups at inner-step boundaries
+(`b_axis` measures it); b matters to callers that launch every inner step
+on its own (hsumma_local_update), where a larger b means fewer C round trips.
 
 Results are cached as JSON (path from $HSUMMA_TUNE_CACHE or an argument),
 keyed by the shape.
@@ -37,6 +41,10 @@ CANDIDATES = [
     ("fp64_64x64x16", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=16)),
     ("fp64_64x64x32", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=32)),
     ("fp64_32x32x16", dict(prec=hs.FP64, tile_m=32, tile_n=32, kc=16)),
+    ("fp64_128x128x16_w8", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=16, waves=8)),
+    ("fp64_128x256x16", dict(prec=hs.FP64, tile_m=128, tile_n=256, kc=16)),
+    ("fp64_64x256x16", dict(prec=hs.FP64, tile_m=64, tile_n=256, kc=16)),
+    ("fp64_256x64x16", dict(prec=hs.FP64, tile_m=256, tile_n=64, kc=16)),
     ("fp64_128x128x16_persistent", dict(prec=hs.FP64, tile_m=128, tile_n=128, kc=16,
                                         persistent=1)),
     ("fp64_64x64x16_persistent", dict(prec=hs.FP64, tile_m=64, tile_n=64, kc=16, persistent=1)),
@@ -45,7 +53,14 @@ CANDIDATES = [
 ]
 NAMES = [c[0] for c in CANDIDATES]
 DEFAULT = "fp64_128x128x16"   # what the library picks without tuning (large shapes)
-SPLIT_MAX_SIGMA = 2.0
+SPLIT_MAX_SIGMA = 2.0         # spread up to which the splits carry every panel (a feature)
+
+
+def library_default(shape) -> str:
+    """The configuration the library picks without tuning (hsumma_plan with
+    no tile options): 64 x 64 macro-tiles when m or n is below 512."""
+    s = shape if isinstance(shape, dict) else shape.__dict__
+    return "fp64_64x64x16" if (s["m"] < 512 or s["n"] < 512) else DEFAULT
 
 
 @dataclass(frozen=True)
@@ -65,8 +80,9 @@ class Shape:
 
 
 def allowed(shape: Shape, name: str) -> bool:
-    # the split forms' FP64 accuracy is tested up to this value spread
-    return not (name.startswith("split_") and shape.sigma > SPLIT_MAX_SIGMA)
+    # every candidate computes an FP64-accurate product: the split forms send
+    # the panels their slice-count model cannot carry to the FP64 kernel
+    return name in NAMES
 
 
 def operands(shape: Shape, seed: int = 0):
@@ -164,6 +180,46 @@ def tune(shape: Shape, cache: Cache | None = None, reps: int = 3) -> tuple[str, 
         hit = cache.get(shape)
     name = hit["best"]
     return name, dict(CANDIDATES)[name]
+
+
+def b_axis(n: int = 4096, P: int = 4, Q: int = 4, G: int = 4, M: int = 512,
+           bs=(32, 64, 128, 256, 512), reps: int = 5) -> dict:
+    """Time of one outer update (ms) and of the same k-range as separate
+    local updates (ms per outer block) for each inner block b | M, FP64."""
+    import torch
+    sh = Shape(n, n, n, P, Q, G, M)
+    A, B, C = operands(sh, 1306)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for b in bs:
+        if b > M or M % b:
+            continue
+        plan = hs.Plan(n, P, Q, G, b, M)
+        ws = plan.workspace()
+        steps = M // b
+
+        def outer():
+            plan.outer_update(0, A, B, C, ws=ws)
+
+        def local():
+            for s in range(steps):
+                plan.local_update(s, A, B, C, ws=ws)
+        res = {}
+        for nm, fn in (("outer_ms", outer), ("local_ms", local)):
+            fn()
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            res[nm] = sorted(ts)[len(ts) // 2]
+        out[b] = res
+        plan.close()
+    return out
 
 
 def valid_groups(P: int, Q: int) -> list[int]:
@@ -286,7 +342,13 @@ def main(argv=None):
     gp.add_argument("--M", type=int, default=256)
     gp.add_argument("--steps", type=int, default=2)
     gp.add_argument("--no-sample", action="store_true", help="model only (no GPU)")
+    bp = sub.add_parser("baxis", help="outer vs local update time over the inner block b")
+    bp.add_argument("--n", type=int, default=4096)
+    bp.add_argument("--M", type=int, default=512)
     args = ap.parse_args(argv)
+    if args.cmd == "baxis":
+        print(json.dumps(b_axis(args.n, M=args.M), indent=1, sort_keys=True))
+        return
     res = {"shape": dict(n=args.n, P=args.P, Q=args.Q, b=args.b, M=args.M),
            "model": {name: select_groups_by_model(args.n, args.P, args.Q, args.b, args.M, **pf)
                      for name, pf in PLATFORMS.items()}}

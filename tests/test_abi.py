@@ -269,3 +269,12 @@ def test_lu_plans_validate_and_size_their_workspace():
     assert hs.lib().hsumma_lu(p._h, A, 1000, ws, p.workspace_size - 1, None) == hs.ERR_WORKSPACE
     assert hs.lib().hsumma_lu(p._h, A, 999, ws, p.workspace_size, None) == hs.ERR_INVALID
     p.close(); q.close()
+
+
+def test_plans_accept_the_compiled_tiles_and_wave_counts():
+    for tm, tn, kc, w in [(128, 256, 16, 0), (64, 256, 16, 0), (256, 64, 16, 0),
+                          (128, 128, 16, 8), (128, 128, 16, 4)]:
+        hs.Plan(1024, 2, 2, 4, 64, 128, tile_m=tm, tile_n=tn, kc=kc, waves=w).close()
+    for tm, tn, kc, w in [(256, 256, 16, 0), (128, 128, 16, 2), (128, 128, 16, 16)]:
+        with pytest.raises(hs.HsummaError):
+            hs.Plan(1024, 2, 2, 4, 64, 128, tile_m=tm, tile_n=tn, kc=kc, waves=w)

@@ -123,13 +123,18 @@ def test_schedule_invariance_bitwise():
     for c in configs:
         p = hs.Plan(n, c["P"], c["Q"], c["G"], 32, c["M"])
         assert np.array_equal(_run(p, A, B), ref), c
-    for tm, tn, kc in [(128, 128, 16), (128, 128, 32), (64, 64, 32), (128, 64, 16),
-                       (64, 128, 16), (32, 32, 16), (256, 128, 16), (256, 128, 8)]:
-        p = hs.Plan(n, 4, 4, 4, 32, 64, tile_m=tm, tile_n=tn, kc=kc)
-        assert np.array_equal(_run(p, A, B), ref), (tm, tn, kc)
+    for tm, tn, kc, w in [(128, 128, 16, 0), (128, 128, 32, 0), (64, 64, 32, 0),
+                          (128, 64, 16, 0), (64, 128, 16, 0), (32, 32, 16, 0),
+                          (256, 128, 16, 0), (256, 128, 8, 0), (128, 128, 16, 8),
+                          (128, 256, 16, 0), (64, 256, 16, 0), (256, 64, 16, 0)]:
+        p = hs.Plan(n, 4, 4, 4, 32, 64, tile_m=tm, tile_n=tn, kc=kc, waves=w)
+        assert np.array_equal(_run(p, A, B), ref), (tm, tn, kc, w)
         # 1 x 2 grid: 512 x 256 tiles, so every macro-tile is full
-        p = hs.Plan(n, 1, 2, 1, 32, 64, tile_m=tm, tile_n=tn, kc=kc)
-        assert np.array_equal(_run(p, A, B), ref), ("full", tm, tn, kc)
+        p = hs.Plan(n, 1, 2, 1, 32, 64, tile_m=tm, tile_n=tn, kc=kc, waves=w)
+        assert np.array_equal(_run(p, A, B), ref), ("full", tm, tn, kc, w)
+        # the register-staged kernel of the same configuration
+        p = hs.Plan(n, 2, 2, 1, 32, 64, tile_m=tm, tile_n=tn, kc=kc, waves=w, staged=1)
+        assert np.array_equal(_run(p, A, B), ref), ("staged", tm, tn, kc, w)
     p = hs.Plan(n, 4, 4, 4, 32, 64, persistent=1)
     assert np.array_equal(_run(p, A, B), ref)
     p = hs.Plan(n, 4, 4, 4, 32, 64, dist=hs.DIST_BLOCK_CYCLIC, nb=64)
