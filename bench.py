@@ -255,32 +255,42 @@ def bench_workloads(names, args, stream):
                 del plan, ws
             del dA, dB, dC
         elif wl == "lu":
-            n, P, Q, G, b, M = 16384, 16, 16, 16, 64, 1024
+            n, P, Q, G = 16384, 16, 16, 16
             A0 = gpu_uniform((n, n), 2013)
             A0 += torch.diag(A0.abs().sum(dim=1) + 1.0)     # diagonally dominant
             dA = torch.empty_like(A0)
-            plan = hs.LuPlan(n, P, Q, G, b, M)
-            ws = plan.workspace()
-            times = []
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            for rep in range(args.warmup + args.steps):
-                with torch.cuda.stream(stream):
-                    dA.copy_(A0)
-                    e0.record(stream)
-                    plan.factor(dA, ws, stream=stream)
-                    e1.record(stream)
-                torch.cuda.synchronize()
-                if rep >= args.warmup:
-                    times.append(e0.elapsed_time(e1))
-            ms = sum(times) / len(times)
-            flops = 2.0 * n ** 3 / 3.0
-            out["lu"] = {"workload": "LU without pivoting, n=16384, 16x16 grid, G=16, b=64, "
-                                     "M=1024, diagonally dominant U[-1,1], FP64",
-                         "ms_per_step": round(ms, 3),
-                         "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
-                         "frac_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP64, 4)}
-            log("lu: %.3f ms, %.1f GFLOP/s" % (ms, out["lu"]["gflops"]))
-            del A0, dA, plan, ws
+            # each schedule at its fastest (b, M) of a sweep over b in {16, 32,
+            # 64} and M in {512, 1024, 2048}; the plain one also at the
+            # look-ahead's (b, M)
+            for la, b, M, name in ((0, 32, 512, "lu"), (0, 32, 2048, "lu_M2048"),
+                                   (1, 32, 2048, "lu_lookahead")):
+                plan = hs.LuPlan(n, P, Q, G, b, M, lookahead=la)
+                ws = plan.workspace()
+                times = []
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                for rep in range(args.warmup + args.steps):
+                    with torch.cuda.stream(stream):
+                        dA.copy_(A0)
+                        e0.record(stream)
+                        plan.factor(dA, ws, stream=stream)
+                        e1.record(stream)
+                    torch.cuda.synchronize()
+                    if rep >= args.warmup:
+                        times.append(e0.elapsed_time(e1))
+                ms = sum(times) / len(times)
+                flops = 2.0 * n ** 3 / 3.0
+                out[name] = {"workload": "LU without pivoting, n=16384, 16x16 grid, G=16, "
+                                         "b=%d, M=%d, diagonally dominant U[-1,1], FP64" % (b, M)
+                                         + (", panel factorisation overlapped with the "
+                                            "trailing update (second stream)" if la else ""),
+                             "ms_per_step": round(ms, 3),
+                             "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                             "frac_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP64, 4)}
+                log("%s: %.3f ms, %.1f GFLOP/s" % (name, ms, out[name]["gflops"]))
+                plan.close()
+                del plan, ws
+            del A0, dA
         torch.cuda.synchronize()
     return out
 

@@ -111,7 +111,12 @@ typedef struct {
                       /* 0 = direct-to-LDS loads where alignment allows         */
   int32_t waves;      /* FP64 path: waves per workgroup of the macro-tile's     */
                       /* kernel; 0 => the tile's first compiled configuration   */
-  int32_t reserved[3];
+  int32_t lookahead;  /* hsumma_lu: 1 = factor the next panel while the rest of */
+                      /* the trailing update runs on a second stream            */
+  int32_t wgs_per_cu; /* persistent launches: workgroups per CU, at most what   */
+                      /* fits; 0 => what fits.  Fewer leave room on every CU    */
+                      /* for concurrent work (hsumma_lu's look-ahead)           */
+  int32_t reserved[1];
 } hsumma_opts;
 
 /* Fill *o with defaults (all zero: square, block, FP64, default tiles). */
@@ -290,6 +295,18 @@ int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k
  * factors.  The plan is host memory; ws (hsumma_lu_workspace_size() bytes,
  * 256-byte aligned) holds the negated panel L21 (n x M doubles) and the
  * trailing updates' workspace.  Asynchronous on `stream`.
+ *
+ * opts.lookahead = 1 overlaps the factorisation of each outer panel with the
+ * previous trailing update (the overlap of panel work and computation the
+ * paper names as future work, Sec. VI): the trailing update is split into
+ * the next panel's block rows and columns, done first on `stream`, and the
+ * rest, done on a second stream while the next panel is factored on
+ * `stream`; the L21 panel is double-buffered (two n x M buffers in ws).  The
+ * plan then creates one non-blocking HIP stream and two events on its first
+ * hsumma_lu call (on that device; hsumma_lu_plan_destroy releases them), and
+ * every later call must be on the same device.  Results are the same bits as
+ * without look-ahead.  hsumma_lu returns once all work is ordered before
+ * `stream`'s next command.
  */
 typedef struct hsumma_lu_plan_s* hsumma_lu_plan_t;
 int hsumma_lu_plan(hsumma_lu_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, int64_t b,

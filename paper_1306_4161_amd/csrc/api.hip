@@ -257,6 +257,7 @@ int launch_grid(hsumma_plan_t p, bool persistent, int occ, int* grid) {
     int dev = 0, cus = 0;
     HS_CHECK_HIP(hipGetDevice(&dev));
     HS_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (p->opts.wgs_per_cu > 0) occ = std::min(occ, (int)p->opts.wgs_per_cu);
     *grid = (int)std::min<int64_t>(*grid, (int64_t)cus * std::max(1, occ));
     *grid = std::max(8, (*grid / 8) * 8);
   }
@@ -515,6 +516,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
       o.prec != HSUMMA_SPLIT_INT8)
     return invalid("unknown precision");
   if (o.nb < 0) return invalid("nb must be >= 0");
+  if (o.wgs_per_cu < 0) return invalid("wgs_per_cu must be >= 0");
   int I = 0, J = 0;
   if (!hs::factor_groups(P, Q, G, &I, &J))
     return invalid("G cannot be arranged as I x J groups with I | P and J | Q");

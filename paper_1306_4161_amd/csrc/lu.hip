@@ -144,55 +144,59 @@ __global__ __launch_bounds__(64) void lu_diag_kernel(double* A, int64_t lda, int
   }
 }
 
-// L21 = A21 U11^-1 for the rows j + V + 64 * blockIdx.x + lane (U11 read from
-// the factored block), in place and negated into negL.
+// The two triangular solves that depend only on the factored diagonal block,
+// in one launch (straight-line code: every step works on the shrinking
+// triangle only).  Workgroups [0, nrow): L21 = A21 U11^-1 for the rows
+// j + V + 64 * blockIdx.x + lane (U11 from LDS), in place and negated into
+// negL.  The rest: U12 = L11^-1 A12 for the columns c0 + 64 * (blockIdx.x -
+// nrow) + lane, with L11 kept transposed in LDS so that the multipliers of
+// one step are contiguous.
 template <int V>
-__global__ __launch_bounds__(64) void lu_l21_kernel(double* A, int64_t lda, int n, int j,
-                                                     double* negL, int64_t ldl, int J) {
-  __shared__ double U[V][V + 1];
+__global__ __launch_bounds__(64) void lu_solve_kernel(double* A, int64_t lda, int n, int j,
+                                                       int nrow, int c0, double* negL,
+                                                       int64_t ldl, int J) {
+  __shared__ double T[V][V + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < V * V; e += 64) U[e / V][e % V] = A[(int64_t)(j + e / V) * lda + j + e % V];
+  const bool rows = (int)blockIdx.x < nrow;
+  const double* D = A + (int64_t)j * lda + j;
+  for (int e = t; e < V * V; e += 64) {
+    const double d = D[(int64_t)(e / V) * lda + e % V];
+    if (rows) T[e / V][e % V] = d;
+    else T[e % V][e / V] = d;
+  }
   __syncthreads();
-  const int r = j + V + (int)blockIdx.x * 64 + t;
-  if (r >= n) return;
   double x[V];
-  double* row = A + (int64_t)r * lda + j;
+  if (rows) {
+    const int r = j + V + (int)blockIdx.x * 64 + t;
+    if (r >= n) return;
+    double* row = A + (int64_t)r * lda + j;
 #pragma unroll
-  for (int c = 0; c < V; ++c) x[c] = row[c];
+    for (int c = 0; c < V; ++c) x[c] = row[c];
 #pragma unroll
-  for (int k = 0; k < V; ++k) {
-    x[k] = x[k] / U[k][k];
+    for (int k = 0; k < V; ++k) {
+      x[k] = x[k] / T[k][k];
 #pragma unroll
-    for (int c = k + 1; c < V; ++c) x[c] = x[c] - x[k] * U[k][c];
+      for (int c = k + 1; c < V; ++c) x[c] = x[c] - x[k] * T[k][c];
+    }
+    double* nl = negL + (int64_t)(r - J) * ldl + (j - J);
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      row[c] = x[c];
+      nl[c] = -x[c];
+    }
+    return;
   }
-  double* nl = negL + (int64_t)(r - J) * ldl + (j - J);
+  const int col = c0 + ((int)blockIdx.x - nrow) * 64 + t;
+  if (col >= n) return;
+  double* cp = A + (int64_t)j * lda + col;
 #pragma unroll
-  for (int c = 0; c < V; ++c) {
-    row[c] = x[c];
-    nl[c] = -x[c];
-  }
-}
-
-// U12 = L11^-1 A12 for the columns [c0, c1): one column per lane; L11 is kept
-// transposed in LDS so that the multipliers of one step are contiguous.
-template <int V>
-__global__ __launch_bounds__(64) void lu_u12_kernel(double* A, int64_t lda, int j, int c0,
-                                                     int c1) {
-  __shared__ double Lt[V][V + 2];
-  const int t = threadIdx.x;
-  for (int e = t; e < V * V; e += 64) Lt[e % V][e / V] = A[(int64_t)(j + e / V) * lda + j + e % V];
-  __syncthreads();
-  const int col = c0 + (int)blockIdx.x * 64 + t;
-  if (col >= c1) return;
-  double y[V];
-#pragma unroll
-  for (int r = 0; r < V; ++r) y[r] = A[(int64_t)(j + r) * lda + col];
+  for (int r = 0; r < V; ++r) x[r] = cp[(int64_t)r * lda];
 #pragma unroll
   for (int k = 0; k < V; ++k)
 #pragma unroll
-    for (int r = k + 1; r < V; ++r) y[r] = y[r] - Lt[k][r] * y[k];
+    for (int r = k + 1; r < V; ++r) x[r] = x[r] - T[k][r] * x[k];
 #pragma unroll
-  for (int r = 0; r < V; ++r) A[(int64_t)(j + r) * lda + col] = y[r];
+  for (int r = 0; r < V; ++r) cp[(int64_t)r * lda] = x[r];
 }
 
 // The panel steps of one inner block [j, j + v): the fast kernels when v is
@@ -203,12 +207,10 @@ hipError_t lu_panel_step(double* A, int64_t lda, int n, int j, int v, double* ne
   auto fast = [&](auto vc) {
     constexpr int V = decltype(vc)::value;
     hipLaunchKernelGGL(lu_diag_kernel<V>, dim3(1), dim3(64), 0, s, A, lda, j);
-    if (below > 0)
-      hipLaunchKernelGGL(lu_l21_kernel<V>, dim3((below + 63) / 64), dim3(64), 0, s, A, lda, n, j,
-                         negL, ldl, J);
-    if (right > 0)
-      hipLaunchKernelGGL(lu_u12_kernel<V>, dim3((right + 63) / 64), dim3(64), 0, s, A, lda, j,
-                         j + v, n);
+    const int nrow = (below + 63) / 64, ncol = (right + 63) / 64;
+    if (nrow + ncol > 0)
+      hipLaunchKernelGGL(lu_solve_kernel<V>, dim3(nrow + ncol), dim3(64), 0, s, A, lda, n, j,
+                         nrow, j + v, negL, ldl, J);
   };
   if (v == 64) fast(std::integral_constant<int, 64>{});
   else if (v == 32) fast(std::integral_constant<int, 32>{});
@@ -232,7 +234,14 @@ namespace {
 
 struct LuOuter {
   int64_t J, w;
-  hsumma_plan_t trailing = nullptr;   // C = A[J+w:, J+w:], k = w (null when empty)
+  int64_t w2 = 0;                     // width of the next outer panel (0: last panel)
+  // without look-ahead: C = A[J+w:, J+w:], k = w (null when empty)
+  hsumma_plan_t trailing = nullptr;
+  // with look-ahead, the same update in three parts: the next panel's rows
+  // and columns first, the rest concurrently with that panel's factorisation
+  hsumma_plan_t cross_rows = nullptr;   // C = A[J+w:J+w+w2, J+w:]
+  hsumma_plan_t cross_cols = nullptr;   // C = A[J+w+w2:, J+w:J+w+w2]
+  hsumma_plan_t rest = nullptr;         // C = A[J+w+w2:, J+w+w2:]
 };
 
 int lu_invalid(const std::string& msg) {
@@ -244,13 +253,62 @@ int lu_invalid(const std::string& msg) {
 
 struct hsumma_lu_plan_s {
   int64_t n = 0, b = 0, M = 0;
+  bool lookahead = false;
   std::vector<LuOuter> outer;
-  size_t off_negL = 0, off_sub = 0, sub_bytes = 0, ws_bytes = 0;
+  size_t off_negL = 0, negL_bytes = 0, off_sub = 0, off_aux = 0, sub_bytes = 0, aux_bytes = 0,
+         ws_bytes = 0;
+  // look-ahead: a second stream and two events, made on first use on a device
+  int device = -1;
+  hipStream_t aux = nullptr;
+  hipEvent_t panel_done = nullptr, rest_done = nullptr;
   ~hsumma_lu_plan_s() {
     for (auto& o : outer)
-      if (o.trailing) hsumma_plan_destroy(o.trailing);
+      for (hsumma_plan_t q : {o.trailing, o.cross_rows, o.cross_cols, o.rest})
+        if (q) hsumma_plan_destroy(q);
+    if (aux) {
+      int cur = -1;
+      if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+      if (device >= 0 && device != cur) (void)hipSetDevice(device);
+      (void)hipEventDestroy(panel_done);
+      (void)hipEventDestroy(rest_done);
+      (void)hipStreamDestroy(aux);
+      if (cur >= 0 && device != cur) (void)hipSetDevice(cur);
+    }
   }
 };
+
+namespace {
+
+// An HSUMMA plan for C (rows x cols) += A (rows x k) B (k x cols) on the
+// P x Q grid (clamped to the block) with G groups where they can be arranged;
+// *need grows to its workspace size.
+int update_plan(int64_t rows, int64_t cols, int64_t k, int32_t P, int32_t Q, int32_t G,
+                int64_t b, const hsumma_opts& o, bool concurrent, hsumma_plan_t* out,
+                size_t* need) {
+  hsumma_opts t = o;
+  t.m = rows;
+  t.k = k;
+  t.lookahead = 0;
+  if (concurrent) {
+    // runs beside the panel kernels: a persistent launch that leaves room
+    // on every CU (one workgroup per CU unless the caller says otherwise)
+    t.persistent = 1;
+    if (!t.wgs_per_cu) t.wgs_per_cu = 1;
+  }
+  const int32_t tp = (int32_t)std::min<int64_t>(P, rows), tq = (int32_t)std::min<int64_t>(Q, cols);
+  int I = 0, Jg = 0;
+  const int32_t tg = hs::factor_groups(tp, tq, G, &I, &Jg) ? G : 1;
+  const int64_t tb = std::min(b, k);
+  const int64_t tM = (k + tb - 1) / tb * tb;
+  int rc = hsumma_plan(out, cols, tp, tq, tg, tb, tM, &t);
+  if (rc) return rc;
+  size_t bytes = 0;
+  hsumma_workspace_size(*out, &bytes);
+  *need = std::max(*need, bytes);
+  return HSUMMA_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -269,39 +327,41 @@ int hsumma_lu_plan(hsumma_lu_plan_t* out, int64_t n, int32_t P, int32_t Q, int32
   hsumma_lu_plan_s* p = new (std::nothrow) hsumma_lu_plan_s();
   if (!p) return lu_invalid("out of host memory");
   p->n = n; p->b = b; p->M = M;
-  size_t sub = 256;
+  p->lookahead = o.lookahead != 0;
+  size_t sub = 256, aux = 256;
   for (int64_t J = 0; J < n; J += M) {
     LuOuter lo;
     lo.J = J;
     lo.w = std::min(M, n - J);
-    const int64_t rest = n - J - lo.w;
-    if (rest > 0) {
-      // the trailing update: a rest x rest block, k = w, on the P x Q grid
-      // (clamped to the block) with G groups where they can be arranged
-      hsumma_opts t = o;
-      t.m = rest;
-      t.k = lo.w;
-      const int32_t tp = (int32_t)std::min<int64_t>(P, rest), tq = (int32_t)std::min<int64_t>(Q, rest);
-      int I = 0, Jg = 0;
-      const int32_t tg = hs::factor_groups(tp, tq, G, &I, &Jg) ? G : 1;
-      const int64_t tb = std::min(b, lo.w);
-      const int64_t tM = (lo.w + tb - 1) / tb * tb;
-      int rc = hsumma_plan(&lo.trailing, rest, tp, tq, tg, tb, tM, &t);
-      if (rc) {
-        delete p;
-        return rc;
-      }
-      size_t need = 0;
-      hsumma_workspace_size(lo.trailing, &need);
-      sub = std::max(sub, need);
+    const int64_t tail = n - J - lo.w;
+    int rc = HSUMMA_OK;
+    if (tail > 0 && !p->lookahead) {
+      rc = update_plan(tail, tail, lo.w, P, Q, G, b, o, false, &lo.trailing, &sub);
+    } else if (tail > 0) {
+      lo.w2 = std::min(M, tail);
+      const int64_t rest = tail - lo.w2;
+      rc = update_plan(lo.w2, tail, lo.w, P, Q, G, b, o, false, &lo.cross_rows, &sub);
+      if (!rc && rest > 0)
+        rc = update_plan(rest, lo.w2, lo.w, P, Q, G, b, o, false, &lo.cross_cols, &sub);
+      if (!rc && rest > 0)
+        rc = update_plan(rest, rest, lo.w, P, Q, G, b, o, true, &lo.rest, &aux);
     }
     p->outer.push_back(lo);
+    if (rc) {
+      delete p;
+      return rc;
+    }
   }
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  // the negated L21 panel: two buffers with look-ahead (the next panel is
+  // written while the rest of the trailing update still reads this one)
+  p->negL_bytes = al((size_t)n * (size_t)M * sizeof(double));
   p->off_negL = 0;
-  p->off_sub = al((size_t)n * (size_t)M * sizeof(double));
+  p->off_sub = p->negL_bytes * (p->lookahead ? 2 : 1);
   p->sub_bytes = al(sub);
-  p->ws_bytes = p->off_sub + p->sub_bytes;
+  p->off_aux = p->off_sub + p->sub_bytes;
+  p->aux_bytes = p->lookahead ? al(aux) : 0;
+  p->ws_bytes = p->off_aux + p->aux_bytes;
   *out = p;
   return HSUMMA_OK;
 }
@@ -325,16 +385,38 @@ int hsumma_lu(hsumma_lu_plan_t p, double* A, int64_t lda, void* ws, size_t ws_by
   }
   if (((uintptr_t)ws) & 255) return lu_invalid("workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = p->n, M = p->M;
-  double* negL = (double*)((uint8_t*)ws + p->off_negL);
-  void* sub = (uint8_t*)ws + p->off_sub;
   auto check = [&](hipError_t e, const char* what) {
     if (e == hipSuccess) return HSUMMA_OK;
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return HSUMMA_ERR_DEVICE;
   };
-  for (const LuOuter& o : p->outer) {
+  if (p->lookahead) {
+    int dev = 0;
+    int rc = check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (p->aux && p->device != dev) {
+      set_error("an LU plan with look-ahead is used on one device only");
+      return HSUMMA_ERR_INVALID;
+    }
+    if (!p->aux) {
+      if ((rc = check(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking), "aux stream")))
+        return rc;
+      if ((rc = check(hipEventCreateWithFlags(&p->panel_done, hipEventDisableTiming), "event")))
+        return rc;
+      if ((rc = check(hipEventCreateWithFlags(&p->rest_done, hipEventDisableTiming), "event")))
+        return rc;
+      p->device = dev;
+    }
+  }
+  const int64_t n = p->n, M = p->M;
+  uint8_t* w8 = (uint8_t*)ws;
+  void* sub = w8 + p->off_sub;
+  void* auxws = w8 + p->off_aux;
+  bool rest_pending = false;
+  for (size_t oi = 0; oi < p->outer.size(); ++oi) {
+    const LuOuter& o = p->outer[oi];
     const int64_t J = o.J, w = o.w;
+    double* negL = (double*)(w8 + p->off_negL + (p->lookahead ? (oi & 1) * p->negL_bytes : 0));
     for (int64_t j = J; j < J + w; j += p->b) {
       const int64_t v = std::min(p->b, J + w - j);
       const int64_t below = n - j - v;
@@ -359,12 +441,47 @@ int hsumma_lu(hsumma_lu_plan_t p, double* A, int64_t lda, void* ws, size_t ws_by
         if (rc) return rc;
       }
     }
-    // the trailing matrix: one HSUMMA outer update with k = w
-    if (o.trailing) {
-      int rc = hsumma_outer_update(o.trailing, 0, negL + w * M, M, A + J * lda + (J + w), lda,
-                                   A + (J + w) * lda + (J + w), lda, sub, p->sub_bytes, stream);
-      if (rc) return rc;
+    const double* L21 = negL + w * M;          // rows J + w .. n of -L21
+    const double* U12 = A + J * lda + (J + w);  // rows J .. J + w of U, right of the panel
+    if (!p->lookahead) {
+      if (o.trailing) {
+        int rc = hsumma_outer_update(o.trailing, 0, L21, M, U12, lda, A + (J + w) * lda + (J + w),
+                                     lda, sub, p->sub_bytes, stream);
+        if (rc) return rc;
+      }
+      continue;
     }
+    if (!o.cross_rows) continue;
+    // the previous panel's rest of the trailing update covers this one's
+    // trailing block: it must be done before any part of the new update
+    if (rest_pending) {
+      int rc = check(hipStreamWaitEvent(s, p->rest_done, 0), "wait for the trailing update");
+      if (rc) return rc;
+      rest_pending = false;
+    }
+    const int64_t w2 = o.w2;
+    if (o.rest) {
+      // the rest on the second stream, once this panel's factors are ready
+      int rc = check(hipEventRecord(p->panel_done, s), "record panel");
+      if (!rc) rc = check(hipStreamWaitEvent(p->aux, p->panel_done, 0), "wait panel");
+      if (!rc) rc = hsumma_outer_update(o.rest, 0, L21 + w2 * M, M, U12 + w2, lda,
+                                        A + (J + w + w2) * lda + (J + w + w2), lda, auxws,
+                                        p->aux_bytes, (void*)p->aux);
+      if (!rc) rc = check(hipEventRecord(p->rest_done, p->aux), "record rest");
+      if (rc) return rc;
+      rest_pending = true;
+    }
+    // the next panel's rows and columns on this stream, then its factorisation
+    int rc = hsumma_outer_update(o.cross_rows, 0, L21, M, U12, lda, A + (J + w) * lda + (J + w),
+                                 lda, sub, p->sub_bytes, stream);
+    if (!rc && o.cross_cols)
+      rc = hsumma_outer_update(o.cross_cols, 0, L21 + w2 * M, M, U12, lda,
+                               A + (J + w + w2) * lda + (J + w), lda, sub, p->sub_bytes, stream);
+    if (rc) return rc;
+  }
+  if (rest_pending) {
+    int rc = check(hipStreamWaitEvent(s, p->rest_done, 0), "wait for the trailing update");
+    if (rc) return rc;
   }
   return HSUMMA_OK;
 }

@@ -70,6 +70,9 @@ def test_plan_rejects_unknown_tile_and_enum():
         hs.Plan(256, 2, 2, 1, 32, dist=7)
     with pytest.raises(hs.HsummaError):
         hs.Plan(256, 2, 2, 1, 32, prec=9)
+    with pytest.raises(hs.HsummaError) as ei:
+        hs.Plan(256, 2, 2, 1, 32, wgs_per_cu=-1)
+    assert "wgs_per_cu" in str(ei.value)
 
 
 PLAN_CASES = [

@@ -91,3 +91,47 @@ def test_n4096_on_a_grid_sampled_backward_error(prec):
     # the leading 1024 x 1024 block (its factors are the leading block's)
     ref = lu_ref.lu_nopivot(A[:1024, :1024])
     assert np.max(np.abs(LU[:1024, :1024] - ref) / (np.abs(ref) + 1.0)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,P,Q,G,b,M", [(256, 1, 1, 1, 32, 64), (300, 2, 2, 4, 64, 128),
+                                         (257, 3, 2, 6, 16, 48), (130, 2, 2, 1, 64, 64),
+                                         (64, 1, 1, 1, 64, 64), (2100, 4, 4, 4, 64, 512)])
+def test_lookahead_same_bits_as_plain(n, P, Q, G, b, M):
+    # the look-ahead schedule splits each trailing update into three blocks
+    # of the same C += (-L21) U12 with the same k order per entry: in FP64
+    # the factors are the same bits, and the integer factors stay exact
+    _say("case lu look-ahead n=%d grid %dx%d G=%d b=%d M=%d" % (n, P, Q, G, b, M))
+    A = _dominant(n, 500 + n)
+    plain = _factor(A, P, Q, G, b, M)
+    ahead = _factor(A, P, Q, G, b, M, lookahead=1)
+    assert np.array_equal(plain, ahead)
+    L0, U0 = _integer_factors(n, 200 + n)
+    L, U = lu_ref.unpack(_factor(L0 @ U0, P, Q, G, b, M, lookahead=1))
+    assert np.array_equal(L, L0) and np.array_equal(U, U0)
+
+
+def test_lookahead_plan_reused_and_split_form():
+    import torch
+    _say("case lu look-ahead reuse n=1536 int8")
+    n = 1536
+    A = _dominant(n, 611)
+    plan = hs.LuPlan(n, 2, 2, 4, 64, 256, lookahead=1)
+    ws = plan.workspace()
+    outs = []
+    for rep in range(2):
+        ws.fill_(0x5A + rep)
+        dA = dev(A)
+        plan.factor(dA, ws)
+        outs.append(host(dA))
+    plan.close()
+    assert np.array_equal(outs[0], outs[1])
+    # the split form: each block of the trailing update takes its own slice
+    # count, so the bits may differ from the plain schedule; both are within
+    # the backward-error bound of the split
+    LU = _factor(A, 2, 2, 4, 64, 256, prec=hs.SPLIT_INT8, lookahead=1)
+    rows, cols = inputs.sample_entries(n, n, 2048, inputs.SEED_SAMPLE,
+                                       range(0, n, 256), range(0, n, 256), per_edge=4)
+    r, s = lu_ref.residual_sampled(LU, A, rows, cols)
+    bound = core.gamma(n) * s + 2 * core.U * np.abs(A[rows, cols]) + (n // 256) * 1e-14 * s
+    assert np.all(r <= bound)
+    torch.cuda.synchronize()

@@ -137,6 +137,8 @@ def test_schedule_invariance_bitwise():
         assert np.array_equal(_run(p, A, B), ref), ("staged", tm, tn, kc, w)
     p = hs.Plan(n, 4, 4, 4, 32, 64, persistent=1)
     assert np.array_equal(_run(p, A, B), ref)
+    p = hs.Plan(n, 4, 4, 4, 32, 64, persistent=1, wgs_per_cu=1)
+    assert np.array_equal(_run(p, A, B), ref)
     p = hs.Plan(n, 4, 4, 4, 32, 64, dist=hs.DIST_BLOCK_CYCLIC, nb=64)
     assert np.array_equal(_run(p, A, B), ref)
 
