@@ -304,9 +304,13 @@ int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k
  * `stream`; the L21 panel is double-buffered (two n x M buffers in ws).  The
  * plan then creates one non-blocking HIP stream and two events on its first
  * hsumma_lu call (on that device; hsumma_lu_plan_destroy releases them), and
- * every later call must be on the same device.  Results are the same bits as
- * without look-ahead.  hsumma_lu returns once all work is ordered before
- * `stream`'s next command.
+ * every later call must be on the same device.  The concurrent part is a
+ * persistent launch of opts.wgs_per_cu workgroups per CU (0 => 1), which
+ * leaves room on every CU for the panel kernels.  FP64: the results are the
+ * same bits as without look-ahead (every entry sums the same products in the
+ * same order).  Split forms: each block of the trailing update takes its own
+ * slice count, so results may differ within the split's error bound.
+ * hsumma_lu returns once all work is ordered before `stream`'s next command.
  */
 typedef struct hsumma_lu_plan_s* hsumma_lu_plan_t;
 int hsumma_lu_plan(hsumma_lu_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, int64_t b,

@@ -613,6 +613,15 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// One C write of a split epilogue as exactly one vector-memory instruction,
+// whatever the compiler would make of a plain store or atomic: the waits
+// that follow the epilogue count these instructions.  `store`: the first
+// panel of a product stores, later ones add (FP64 atomic add, no return).
+__device__ __forceinline__ void c_write(double* dst, double v, int store) {
+  if (store) asm volatile("global_store_dwordx2 %0, %1, off" ::"v"(dst), "v"(v) : "memory");
+  else asm volatile("global_atomic_add_f64 %0, %1, off" ::"v"(dst), "v"(v) : "memory");
+}
+
 // Wait until at most k x PER of this wave's vector-memory instructions are
 // outstanding (k <= KMAX, known only at run time; the count is an immediate).
 template <int PER, int KMAX>
@@ -892,9 +901,9 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
         if (st < nsteps) issue(st, st);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // Every lane issues all NSTORE writes: lanes outside a ragged item write
-    // to their own slot of the dump area, so that the count the next item's
-    // first wait allows for is exact.
+    // Every lane issues all NSTORE writes, each one instruction (c_write):
+    // lanes outside a ragged item write to their own slot of the dump area,
+    // so that the count the next item's first wait allows for is exact.
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int col = wn * 64 + q * 32 + le32;
@@ -904,8 +913,7 @@ __device__ __forceinline__ void slice_bf16_items(const SliceArgs& p, uint8_t* sm
         const double add = ldexp(q ? cp1[v] : cp0[v], ea[v] + fq[q] - 16);
         const bool in = row < it.h && col < it.w;
         double* dst = in ? p.C + (int64_t)(it.r0 + row) * p.ldc + it.c0 + col : p.dump + lane_e;
-        if (p.zero_init) *dst = add;
-        else unsafeAtomicAdd(dst, add);
+        c_write(dst, add, p.zero_init);
       }
     }
     it = nt;
@@ -1378,9 +1386,9 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
         if (st < nsteps) issue(st, st);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // Every lane issues all NSTORE writes: lanes outside a ragged item write
-    // to their own slot of the dump area, so that the count the next item's
-    // first wait allows for is exact.
+    // Every lane issues all NSTORE writes, each one instruction (c_write):
+    // lanes outside a ragged item write to their own slot of the dump area,
+    // so that the count the next item's first wait allows for is exact.
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int col = wn * 64 + q * 32 + le32;
@@ -1391,8 +1399,7 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
         const double add = ldexp(cp, ea[v] + fq[q] - 12);
         const bool in = row < it.h && col < it.w;
         double* dst = in ? p.C + (int64_t)(it.r0 + row) * p.ldc + it.c0 + col : p.dump + lane_e;
-        if (p.zero_init) *dst = add;
-        else unsafeAtomicAdd(dst, add);
+        c_write(dst, add, p.zero_init);
       }
     }
     it = nt;
