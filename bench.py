@@ -390,8 +390,9 @@ def main():
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak,
                                "unit": "TOP/s" if base == "int8" else "TFLOP/s",
                                "frac": round(ach / peak, 4),
-                               "traffic": (committed_traffic("slice_" + base, wl, split_src)
-                                           if name in ("bf16", "int8") else None),
+                               "traffic": (committed_traffic(
+                                   "slice_" + base, wl + ("_uniform" if sigma == 0 else ""),
+                                   split_src) if base in ("bf16", "int8") else None),
                                "kernel": kern,
                                "flops_per_launch": per_launch, "launches_per_step": nouter,
                                "avg_launch_ms": round(pms, 4)}
