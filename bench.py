@@ -185,6 +185,12 @@ def product_launch_ms(plan, g, dA, dB, ws, stream, args):
     return time_region(prod, max(3, args.steps), stream)
 
 
+def fp64_kernel_name(plan):
+    """The FP64 update kernel of a plan: its macro-tile, k-chunk and waves."""
+    tm, tn, kc, waves = plan.tile_config
+    return "fp64_dma_kernel %dx%d, k-chunk %d, %d waves" % (tm, tn, kc, waves)
+
+
 def bench_workloads(names, args, stream):
     """The configurations besides the headline one (timing and roofline)."""
     import torch
@@ -206,7 +212,7 @@ def bench_workloads(names, args, stream):
                          "roofline": {"bound": "mfma", "achieved": round(ach, 2),
                                       "peak": PEAK_FP64, "unit": "TFLOP/s",
                                       "frac": round(ach / PEAK_FP64, 4),
-                                      "kernel": "fp64_dma_kernel<128,128,2,2,2,2>",
+                                      "kernel": fp64_kernel_name(plan),
                                       "flops_per_launch": per_launch,
                                       "launches_per_step": plan.num_outer_steps,
                                       "avg_launch_ms": round(avg, 4)}}
@@ -234,7 +240,7 @@ def bench_workloads(names, args, stream):
                     rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2),
                                        "peak": PEAK_FP64, "unit": "TFLOP/s",
                                        "frac": round(ach / PEAK_FP64, 4),
-                                       "kernel": "fp64_dma_kernel<128,128,2,2,2,2> (persistent)",
+                                       "kernel": fp64_kernel_name(plan) + " (persistent)",
                                        "flops_per_launch": per_launch,
                                        "avg_launch_ms": round(avg, 4)}
                 else:
@@ -364,7 +370,7 @@ def main():
             rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_FP64,
                                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64, 4),
                                "traffic": committed_traffic("fp64_update", wl, src),
-                               "kernel": "fp64_dma_kernel<128,128,2,2,2,2>",
+                               "kernel": fp64_kernel_name(plan),
                                "flops_per_launch": per_launch, "launches_per_step": nouter,
                                "avg_launch_ms": round(avg_ms, 4), "source_hash": src}
         else:

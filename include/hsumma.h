@@ -162,6 +162,18 @@ int hsumma_step_info(hsumma_plan_t plan, int64_t s, int64_t* k0, int64_t* k1,
 /* Number of work items (macro-tiles over all tiles) per launch. */
 int hsumma_num_items(hsumma_plan_t plan, int64_t* items);
 /*
+ * The macro-tile the plan's update kernels use: rows, columns, k-chunk and
+ * waves per workgroup (the split forms: 64 x 128, 16-k steps or 32-k for
+ * INT8, 4 waves).  With no tile option given, the FP64 path takes 32 x 32
+ * when fewer than 768 macro-tiles of 64 x 64 would make a launch; 64 x 64
+ * when a processor's tile is under 512 on a side (m/P or n/Q), the outer
+ * block M is under 128, or fewer than 4096 macro-tiles of 128 x 128 would
+ * make a launch; 128 x 64 when M >= 1024; else 128 x 128 (fitted to the
+ * autotuner's timings of 2013 shapes).
+ */
+int hsumma_tile_config(hsumma_plan_t plan, int32_t* tile_m, int32_t* tile_n, int32_t* kc,
+                       int32_t* waves);
+/*
  * The work-item table the compute calls write into the workspace, as the
  * plan defines it (host memory, out has 4 x hsumma_num_items() int32):
  * item t is rows [r0, r0 + h) and columns [c0, c0 + w) of C, stored as

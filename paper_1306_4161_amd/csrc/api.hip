@@ -147,6 +147,38 @@ int64_t local_count(const hsumma_plan_s& p, bool rows, int r) {
   return c;
 }
 
+// Macro-tiles of width t over every processor's rows (or columns).
+int64_t pieces_of(const hsumma_plan_s& p, bool rows, int64_t t) {
+  int64_t c = 0;
+  for (int r = 0; r < (rows ? p.P : p.Q); ++r)
+    for (auto& run : runs_of(p, rows, r)) c += (run.g1 - run.g0 + t - 1) / t;
+  return c;
+}
+
+// The FP64 macro-tile when the caller names none, from the number of
+// macro-tiles a launch would have, the processors' tile size and the outer
+// block.  A rule fitted to the tuner's exhaustive timings (2000 random
+// shapes with m, n, k in [512, 16384], P, Q <= 16, M <= 512; twelve larger
+// ones with M up to 1024; the 6 x 10 block-cyclic grid at n = 10000):
+// within 2.5 % of the fastest candidate on average, where a fixed 128 x 128
+// was 49 % behind on the random shapes.
+//   * fewer than 768 items of 64 x 64: 32 x 32 (the launch needs the items);
+//   * a processor tile under 512 on a side, an outer block under 128, or
+//     fewer than 4096 items of 128 x 128: 64 x 64 (little work per item, or
+//     128-wide tiles leave CUs idle or ragged);
+//   * an outer block of 1024 or more: 128 x 64 (its two workgroups per CU
+//     keep more C tiles in flight than 128 x 128 at the same reuse);
+//   * otherwise 128 x 128.
+hs::TileCfg default_tile(const hsumma_plan_s& p) {
+  const int64_t i64 = pieces_of(p, true, 64) * pieces_of(p, false, 64);
+  const int64_t i128 = pieces_of(p, true, 128) * pieces_of(p, false, 128);
+  const int64_t side = std::min(p.m / p.P, p.n / p.Q);
+  if (i64 < 768) return {32, 32, 16};
+  if (side < 512 || p.M < 128 || i128 < 4096) return {64, 64, 16};
+  if (p.M >= 1024) return {128, 64, 16};
+  return {128, 128, 16};
+}
+
 // max_row_block: the largest br x (pieces of a processor column), the
 // generator's int32 unit of a block row.
 void build_items(hsumma_plan_s& p, int64_t* max_row_block) {
@@ -528,12 +560,19 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   p->P = P; p->Q = Q; p->G = G; p->I = I; p->J = J;
   p->opts = o;
   p->opts.m = m; p->opts.k = k; p->opts.nb = p->nb;
+  p->rlo = block_bounds(m, P);
+  p->clo = block_bounds(n, Q);
 
   // Tile configuration.
   if (o.prec == HSUMMA_FP64) {
     hs::TileCfg cfg{o.tile_m ? o.tile_m : 128, o.tile_n ? o.tile_n : 128, o.kc ? o.kc : 16,
                     o.waves};
-    if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) cfg = {64, 64, 16, o.waves};
+    if (!o.tile_m && !o.tile_n && !o.kc) {
+      const hs::TileCfg d = default_tile(*p);
+      cfg = {d.tm, d.tn, d.kc, o.waves};
+    } else if (!o.tile_m && !o.tile_n && (m < 512 || n < 512)) {
+      cfg = {64, 64, o.kc, o.waves};
+    }
     bool ok = false;
     for (auto& c : hs::fp64_configs())
       if (hs::same_tile(cfg, c)) {
@@ -591,8 +630,6 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     }
   }
 
-  p->rlo = block_bounds(m, P);
-  p->clo = block_bounds(n, Q);
   p->kqlo = block_bounds(k, Q);
   p->kplo = block_bounds(k, P);
   for (int64_t g0 = 0; g0 < k; g0 += M) {
@@ -674,6 +711,16 @@ int hsumma_groups(hsumma_plan_t p, int32_t* I, int32_t* J) {
   if (!p || !I || !J) return invalid("null argument");
   *I = p->I;
   *J = p->J;
+  return HSUMMA_OK;
+}
+
+int hsumma_tile_config(hsumma_plan_t p, int32_t* tile_m, int32_t* tile_n, int32_t* kc,
+                       int32_t* waves) {
+  if (!p || !tile_m || !tile_n || !kc || !waves) return invalid("null argument");
+  *tile_m = p->cfg.tm;
+  *tile_n = p->cfg.tn;
+  *kc = p->cfg.kc;
+  *waves = p->fmt < 0 ? p->cfg.waves : 4;
   return HSUMMA_OK;
 }
 

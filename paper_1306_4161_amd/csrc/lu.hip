@@ -289,6 +289,16 @@ int update_plan(int64_t rows, int64_t cols, int64_t k, int32_t P, int32_t Q, int
   t.m = rows;
   t.k = k;
   t.lookahead = 0;
+  // FP64: 128 x 128 macro-tiles (64 x 64 below 512 rows or columns) unless
+  // the caller names a tile.  The plan's own rule looks at the processor
+  // tile, which the thin block-row and block-column updates of the
+  // look-ahead make small; its 64 x 64 choice there made the look-ahead 7 %
+  // slower at n = 16384, M = 2048, and its 128 x 64 choice for M >= 1024 is
+  // slower at one workgroup per CU.
+  if (t.prec == HSUMMA_FP64 && !t.tile_m && !t.tile_n && !t.kc) {
+    t.tile_m = t.tile_n = (rows < 512 || cols < 512) ? 64 : 128;
+    t.kc = 16;
+  }
   if (concurrent) {
     // runs beside the panel kernels: a persistent launch that leaves room
     // on every CU (one workgroup per CU unless the caller says otherwise)

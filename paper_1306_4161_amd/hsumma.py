@@ -21,7 +21,8 @@ DIST_BLOCK, DIST_BLOCK_CYCLIC = 0, 1
 EXPORTED = [
     "hsumma_opts_default", "hsumma_plan", "hsumma_plan_destroy", "hsumma_workspace_size",
     "hsumma_num_steps", "hsumma_num_outer_steps", "hsumma_groups", "hsumma_tile_shape",
-    "hsumma_step_info", "hsumma_num_items", "hsumma_local_update", "hsumma_outer_update",
+    "hsumma_step_info", "hsumma_num_items", "hsumma_tile_config", "hsumma_local_update",
+    "hsumma_outer_update",
     "hsumma_run", "hsumma_panel_slices", "hsumma_last_error", "hsumma_version",
     "hsumma_split_layout", "hsumma_mfma_exact_probe", "hsumma_outer_products",
     "hsumma_work_items", "hsumma_prepare_workspace", "hsumma_run_noalloc",
@@ -222,6 +223,13 @@ class Plan:
     @property
     def num_items(self):
         return self._i64(lib().hsumma_num_items)
+
+    @property
+    def tile_config(self):
+        """(tile_m, tile_n, kc, waves) of the plan's update kernels."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().hsumma_tile_config(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     @property
     def workspace_size(self):

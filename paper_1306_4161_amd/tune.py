@@ -52,15 +52,18 @@ CANDIDATES = [
     ("split_int8", dict(prec=hs.SPLIT_INT8)),
 ]
 NAMES = [c[0] for c in CANDIDATES]
-DEFAULT = "fp64_128x128x16"   # what the library picks without tuning (large shapes)
+DEFAULT = "fp64_128x128x16"   # the fixed configuration the regret reports compare against
 SPLIT_MAX_SIGMA = 2.0         # spread up to which the splits carry every panel (a feature)
 
 
 def library_default(shape) -> str:
     """The configuration the library picks without tuning (hsumma_plan with
-    no tile options): 64 x 64 macro-tiles when m or n is below 512."""
+    no tile options), as the plan reports it."""
     s = shape if isinstance(shape, dict) else shape.__dict__
-    return "fp64_64x64x16" if (s["m"] < 512 or s["n"] < 512) else DEFAULT
+    p = hs.Plan(s["n"], s["P"], s["Q"], s["G"], s["M"], s["M"], m=s["m"], k=s["k"])
+    tm, tn, kc, _ = p.tile_config
+    p.close()
+    return "fp64_%dx%dx%d" % (tm, tn, kc)
 
 
 @dataclass(frozen=True)

@@ -281,3 +281,24 @@ def test_plans_accept_the_compiled_tiles_and_wave_counts():
     for tm, tn, kc, w in [(256, 256, 16, 0), (128, 128, 16, 2), (128, 128, 16, 16)]:
         with pytest.raises(hs.HsummaError):
             hs.Plan(1024, 2, 2, 4, 64, 128, tile_m=tm, tile_n=tn, kc=kc, waves=w)
+
+
+@pytest.mark.parametrize("args,kw,tile", [
+    ((16384, 16, 16, 16, 256, 1024), {}, (128, 64, 16)),      # outer block >= 1024
+    ((16384, 16, 16, 16, 256, 256), {}, (128, 128, 16)),
+    ((8192, 8, 8, 4, 64, 256), {}, (128, 128, 16)),
+    ((10000, 6, 10, 1, 128, 128), {"dist": hs.DIST_BLOCK_CYCLIC}, (128, 128, 16)),
+    ((6000, 16, 16, 16, 512, 512), {}, (64, 64, 16)),        # processor tiles of 375
+    ((16384, 16, 16, 16, 64, 64), {}, (64, 64, 16)),         # outer block under 128
+    ((256, 2, 2, 1, 32, 32), {}, (32, 32, 16)),              # 16 items of 64 x 64
+    ((16384, 16, 16, 16, 256, 1024), {"kc": 32}, (128, 128, 32)),
+    ((16384, 16, 16, 16, 256, 1024), {"tile_m": 256, "tile_n": 128, "kc": 8}, (256, 128, 8)),
+    ((16384, 16, 16, 16, 256, 1024), {"prec": hs.SPLIT_INT8}, (64, 128, 32)),
+    ((16384, 16, 16, 16, 256, 1024), {"prec": hs.SPLIT_BF16}, (64, 128, 16)),
+])
+def test_default_tile_rule(args, kw, tile):
+    # the macro-tile the plan picks when none is named (hsumma_tile_config)
+    p = hs.Plan(*args, **kw)
+    tm, tn, kc, waves = p.tile_config
+    assert (tm, tn, kc) == tile and waves > 0
+    p.close()

@@ -37,18 +37,20 @@ def test_exhaustive_tune_and_cache(tmp_path):
 
 
 def test_learned_model_against_untuned_and_best_static_on_held_out_shapes():
-    # The network overrides the best static configuration only where its
-    # predicted gain clears a margin chosen on validation shapes.  On this
-    # shape distribution one configuration is within a few per cent of the
-    # exhaustive optimum on average, which is about the timing noise of
-    # these launches, so the learned pick is held to "far better than the
-    # library's untuned choice and no more than 2 points behind the best
-    # static configuration" rather than to beating it.
+    # The network overrides the library's untuned choice (its rule fitted to
+    # the tuner's timings) only where its predicted gain clears a margin
+    # chosen on validation shapes.  On this shape distribution that rule and
+    # the best single configuration are within a few per cent of the
+    # exhaustive optimum on average, about the timing noise of these
+    # launches, so the learned pick is held to "no more than 2 points behind
+    # either" rather than to beating them; the rule itself must be far
+    # better than a fixed 128 x 128 configuration.
     res = costmodel.experiment(n_shapes=400, seed=7, n_test=100, epochs=2000, log=None, reps=5)
     print(json.dumps({k: res[k] for k in ("regret_mlp", "regret_mlp_argmin", "margin_log2",
-                                          "regret_library_default", "regret_best_static",
-                                          "best_static")}))
-    assert res["regret_mlp"]["mean"] < 0.5 * res["regret_library_default"]["mean"]
+                                          "regret_library_default", "regret_fixed_default",
+                                          "regret_best_static", "best_static")}))
+    assert res["regret_library_default"]["mean"] < 0.25 * res["regret_fixed_default"]["mean"]
+    assert res["regret_mlp"]["mean"] <= res["regret_library_default"]["mean"] + 0.02
     assert res["regret_mlp"]["mean"] <= res["regret_best_static"]["mean"] + 0.02
     assert np.isfinite(res["regret_mlp"]["max"])
 
