@@ -13,11 +13,6 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long-running test")
 
 
-def pytest_collection_modifyitems(config, items):
-    # Order GPU tests so that cheap parity checks run before large ones.
-    pass
-
-
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
