@@ -66,7 +66,7 @@ typedef struct hsumma_plan_s* hsumma_plan_t;
 typedef enum {
   HSUMMA_OK = 0,
   HSUMMA_ERR_INVALID = -1,      /* bad argument or unsupported shape */
-  HSUMMA_ERR_UNSUPPORTED = -2,  /* option not available in this build / device */
+  HSUMMA_ERR_UNSUPPORTED = -2,  /* option not compiled in or not supported by the device */
   HSUMMA_ERR_DEVICE = -3,       /* a HIP call failed (message has its text) */
   HSUMMA_ERR_WORKSPACE = -4     /* workspace missing or too small */
 } hsumma_status;
