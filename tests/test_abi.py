@@ -266,6 +266,14 @@ def test_lu_plans_validate_and_size_their_workspace():
     assert p.workspace_size >= 1000 * 256 * 8 + 16 * ((1000 - 256 + 127) // 128) ** 2
     q = hs.LuPlan(1000, 4, 4, 16, 64, 256, prec=hs.SPLIT_INT8)
     assert q.workspace_size > p.workspace_size       # digit planes of the trailing updates
+    # look-ahead: two L21 buffers and a second region for the concurrent update
+    la = hs.LuPlan(1000, 4, 4, 16, 64, 256, lookahead=1)
+    assert la.workspace_size >= 2 * 1000 * 256 * 8 + 2 * 256
+    assert la.workspace_size > p.workspace_size
+    la.close()
+    one = hs.LuPlan(200, 4, 4, 16, 64, 256, lookahead=1)   # one panel: nothing to overlap
+    assert one.workspace_size >= 2 * 200 * 256 * 8
+    one.close()
     import ctypes
     ws = ctypes.c_void_p(0x7000000)
     A = ctypes.c_void_p(0x100000)
