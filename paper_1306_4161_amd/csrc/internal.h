@@ -34,7 +34,11 @@ struct UpdateArgs {
                        // split forms' FP64 route for a panel they cannot split)
   // items == nullptr: the items are the macro-tiles of one dense
   // dense_m x dense_n block of C, row-major over dense_nc tile columns
-  int32_t dense_m, dense_n, dense_nc;
+  // (dense_items1 of them), then those of a second block of dense_m2 x
+  // dense_n2 right of it (columns dense_n .. dense_n + dense_n2, the same
+  // rows of A from row 0), row-major over dense_nc2 tile columns
+  int32_t dense_m, dense_n, dense_nc, dense_items1;
+  int32_t dense_m2, dense_n2, dense_nc2;
 };
 
 // Parameters of the device-side work-item generator (k_items.hip), which
@@ -87,10 +91,12 @@ hipError_t launch_fp64(const TileCfg& cfg, const UpdateArgs& a, int grid, hipStr
 bool fp64_has_dma(const TileCfg& cfg);
 // C (m x n, ldc) += A (m x k) B (k x n) by the FP64 update kernel over the
 // macro-tiles of C in row-major order (no work-item table): for updates of
-// one dense block, e.g. inside an LU panel.
+// one dense block, e.g. inside an LU panel.  With m2, n2 > 0 the same launch
+// also updates the block of rows [0, m2) and columns [n, n + n2) (B and C
+// then have n + n2 columns): the L-shaped update of an LU panel step.
 hipError_t launch_fp64_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
                              double* C, int64_t ldc, int64_t m, int64_t n, int64_t k,
-                             hipStream_t s);
+                             hipStream_t s, int64_t m2 = 0, int64_t n2 = 0);
 int fp64_occupancy(const TileCfg& cfg);  // workgroups per CU the config is built for
 
 // Split (precision) path.

@@ -53,12 +53,18 @@ struct Fp64Tile {
 };
 
 // Work item idx: from the table, or the idx-th macro-tile (row-major) of
-// the dense block when there is no table.
+// the dense block(s) when there is no table.
 template <int TM, int TN>
 __device__ __forceinline__ WorkItem fetch_item(const UpdateArgs& p, int idx) {
   if (p.items) return p.items[idx];
-  const int tr = idx / p.dense_nc, tc = idx - tr * p.dense_nc;
-  return WorkItem{tr * TM, tc * TN, min(TM, p.dense_m - tr * TM), min(TN, p.dense_n - tc * TN)};
+  if (idx < p.dense_items1) {
+    const int tr = idx / p.dense_nc, tc = idx - tr * p.dense_nc;
+    return WorkItem{tr * TM, tc * TN, min(TM, p.dense_m - tr * TM), min(TN, p.dense_n - tc * TN)};
+  }
+  idx -= p.dense_items1;
+  const int tr = idx / p.dense_nc2, tc = idx - tr * p.dense_nc2;
+  return WorkItem{tr * TM, p.dense_n + tc * TN, min(TM, p.dense_m2 - tr * TM),
+                  min(TN, p.dense_n2 - tc * TN)};
 }
 
 template <int TM, int TN, int KC, int WM, int WN, int OCC>
@@ -515,21 +521,31 @@ bool fp64_has_dma(const TileCfg& cfg) {
 
 hipError_t launch_fp64_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
                              double* C, int64_t ldc, int64_t m, int64_t n, int64_t k,
-                             hipStream_t s) {
-  if (m <= 0 || n <= 0) return hipSuccess;
-  const TileCfg cfg = (m < 512 || n < 512) ? TileCfg{64, 64, 16} : TileCfg{128, 128, 16};
+                             hipStream_t s, int64_t m2, int64_t n2) {
+  if (m2 <= 0 || n2 <= 0) m2 = n2 = 0;
+  if (m <= 0 || n <= 0) {
+    if (!m2) return hipSuccess;
+    // only the second block: it is then the first, shifted by n columns
+    return launch_fp64_dense(A, lda, B + n, ldb, C + n, ldc, m2, n2, k, s);
+  }
+  const bool small = m < 512 || n < 512 || (m2 && (m2 < 512 || n2 < 512));
+  const TileCfg cfg = small ? TileCfg{64, 64, 16} : TileCfg{128, 128, 16};
   UpdateArgs a{};
   a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.C = C; a.ldc = ldc;
   a.items = nullptr;
   a.dense_m = (int32_t)m; a.dense_n = (int32_t)n;
   a.dense_nc = (int32_t)((n + cfg.tn - 1) / cfg.tn);
-  const int64_t nit = (int64_t)((m + cfg.tm - 1) / cfg.tm) * a.dense_nc;
+  a.dense_items1 = (int32_t)((m + cfg.tm - 1) / cfg.tm) * a.dense_nc;
+  a.dense_m2 = (int32_t)m2; a.dense_n2 = (int32_t)n2;
+  a.dense_nc2 = (int32_t)((n2 + cfg.tn - 1) / cfg.tn);
+  const int64_t nit = (int64_t)a.dense_items1 + (int64_t)((m2 + cfg.tm - 1) / cfg.tm) * a.dense_nc2;
   a.nitems = (int32_t)nit;
   a.per_xcd = (int32_t)((nit + 7) / 8);
   a.k0 = 0; a.k1 = k; a.bstep = k; a.zero_init = 0; a.persistent = 0; a.gate = nullptr;
+  // 16-byte DMA units: even k, leading dimensions, column offsets and widths
   const bool dma = !((k | lda | ldb) & 1) && !(((uintptr_t)A | (uintptr_t)B) & 15) &&
                    (int64_t)cfg.tm * lda * 8 < (int64_t(1) << 31) &&
-                   (int64_t)16 * ldb * 8 < (int64_t(1) << 31) && !(n & 1);
+                   (int64_t)16 * ldb * 8 < (int64_t(1) << 31) && !(n & 1) && !(n2 & 1);
   return launch_fp64(cfg, a, 8 * a.per_xcd, s, dma);
 }
 

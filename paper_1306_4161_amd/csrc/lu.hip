@@ -12,7 +12,7 @@
 //   2. U12 = L11^-1 A12 for every column right of the block;
 //   3. the update inside the outer panel, A[j+v:, j+v:J+w] -= L21 U12, and
 //      on the outer panel's own rows right of it, A[j+v:J+w, J+w:] -= L U12
-//      (dense FP64 updates, k = v).
+//      (one dense FP64 launch over the L-shaped block, k = v).
 // Then the trailing matrix A[J+w:, J+w:] -= L21 U12 with k = w is one
 // HSUMMA outer update on the P x Q grid with G groups (any precision form):
 // C is loaded once, held in MFMA accumulators across the w/b inner steps
@@ -433,21 +433,16 @@ int hsumma_lu(hsumma_lu_plan_t p, double* A, int64_t lda, void* ws, size_t ws_by
       int rc = check(hs::lu_panel_step(A, lda, (int)n, (int)j, (int)v, negL, M, (int)J, s),
                      "LU panel launch");
       if (rc) return rc;
-      // inside the outer panel: A[j+v:n, j+v:J+w] += (-L21) U12
+      // in one launch: inside the outer panel, A[j+v:n, j+v:J+w] += (-L21)
+      // U12, and the outer panel's rows right of it, A[j+v:J+w, J+w:n] +=
+      // (-L) U12 (the same -L rows and U12 row block, an L-shaped C)
       const double* nl = negL + (j + v - J) * M + (j - J);
-      if (below > 0 && J + w - j - v > 0) {
+      const int64_t inside = J + w - j - v;
+      if (inside > 0) {
         rc = check(hs::launch_fp64_dense(nl, M, A + j * lda + (j + v), lda,
-                                         A + (j + v) * lda + (j + v), lda, below, J + w - j - v,
-                                         v, s),
+                                         A + (j + v) * lda + (j + v), lda, below, inside, v, s,
+                                         inside, n - J - w),
                    "LU panel update launch");
-        if (rc) return rc;
-      }
-      // the outer panel's rows right of it: A[j+v:J+w, J+w:n] += (-L) U12
-      if (J + w - j - v > 0 && n - J - w > 0) {
-        rc = check(hs::launch_fp64_dense(nl, M, A + j * lda + (J + w), lda,
-                                         A + (j + v) * lda + (J + w), lda, J + w - j - v,
-                                         n - J - w, v, s),
-                   "LU row-block update launch");
         if (rc) return rc;
       }
     }
