@@ -116,3 +116,38 @@ def test_headline_split_meets_gate(workload, prec):
     assert np.all(np.isfinite(Ch[workload["rows"], workload["cols"]]))
     assert sc <= GATE
     _freivalds(workload, Ch)
+
+
+@pytest.fixture(scope="module")
+def stress():
+    import torch
+    _say("headline stress: generating n=%d sigma=4 operands" % N)
+    A = inputs.exponent_spread(N, N, inputs.SEED_A + 1, 4.0)
+    B = inputs.exponent_spread(N, N, inputs.SEED_B + 1, 4.0)
+    edges = [i * N // P for i in range(P)]
+    rows, cols = inputs.sample_entries(N, N, 2048, inputs.SEED_SAMPLE, edges, edges, per_edge=32)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    return dict(A=A, B=B, dA=dA, dB=dB, rows=rows, cols=cols)
+
+
+def test_headline_shape_sigma4_stress(stress):
+    # Exponent spread sigma = 4 at the benchmarked shape, beyond what the
+    # digit splits carry: their panels go to the FP64 kernel.  At this spread
+    # the FP64 product itself no longer meets 1e-14 of (|A||B|)_ij on every
+    # sampled entry (its bound is gamma_K (|A||B|)), so the splits are held
+    # to the FP64 path: within the same bound, no worse than it, and bit for
+    # bit equal to it when every panel took the FP64 route.
+    _say("case headline stress sigma=4 fp64")
+    C64, _ = _run(stress, hs.FP64, M_OUT)
+    s64 = check_sampled(stress["A"], stress["B"], C64, stress["rows"], stress["cols"])
+    _say("  fp64 max scaled err %.3g" % s64)
+    for prec in (hs.SPLIT_BF16, hs.SPLIT_INT8):
+        _say("case headline stress sigma=4 prec=%d" % prec)
+        Ch, slices = _run(stress, prec, M_OUT)
+        sc = check_sampled(stress["A"], stress["B"], Ch, stress["rows"], stress["cols"])
+        _say("  slices %r max scaled err %.3g" % (sorted(set(slices)), sc))
+        assert sc <= max(GATE, s64)
+        if all(x == 0 for x in slices):
+            assert np.array_equal(Ch, C64)
