@@ -132,19 +132,25 @@ def cpu_baseline(A, B, target_s):
                 rows - 1, rows, k, n, dt)}
 
 
+LAST_MEDIAN_MS = [0.0]   # median ms per call of the last time_region
+
+
 def time_region(fn, steps, stream):
-    """ms per call of fn over `steps` calls, HIP events on `stream`."""
+    """Mean ms per call of fn over `steps` calls, HIP events on `stream`
+    (one event between calls, so the median per call is kept too, in
+    LAST_MEDIAN_MS)."""
     import torch
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
-        e0.record(stream)
-        for _ in range(steps):
+        ev[0].record(stream)
+        for i in range(steps):
             fn()
-        e1.record(stream)
+            ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    LAST_MEDIAN_MS[0] = per[steps // 2] if steps % 2 else 0.5 * (per[steps // 2 - 1] + per[steps // 2])
+    return ev[0].elapsed_time(ev[steps]) / steps
 
 
 def sampled_scale(dA, dB, rows, cols):
@@ -352,9 +358,11 @@ def main():
         ws = plan.workspace()
         t0 = time.perf_counter()
         ms = run_plan(hs, plan, pA, pB, dC, ws, stream, args)
+        ms_median = LAST_MEDIAN_MS[0]
         wall = time.perf_counter() - t0
         diff = float(np.max(np.abs(dC.cpu().numpy()[rows, cols] - c64) / sc))
-        rec = {"ms_per_step": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+        rec = {"ms_per_step": round(ms, 3), "ms_per_step_median": round(ms_median, 3),
+               "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                "sigma": sigma, "wall_s": round(wall, 3),
                "max_scaled_diff_vs_fp64": diff,
                "outer_steps": plan.num_outer_steps, "inner_steps": plan.num_steps}
