@@ -84,3 +84,30 @@ def test_results_independent_of_workspace_contents(prec):
         p.local_update(s, A, B, C2, ws=wsp)
     assert torch.equal(C, C2)
     assert np.isfinite(host(C)).all()
+
+
+def test_device_table_equals_host_definition_random_plans():
+    # random shapes, grids, groupings, distributions and precisions (the
+    # strategy of tests/test_items_random.py), each table written by the
+    # device generator into a dirtied workspace
+    import torch
+    from hypothesis import given, settings, HealthCheck
+    from test_items_random import plans
+
+    @settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+    @given(plans())
+    def check(c):
+        d = hs.DIST_BLOCK if c["dist"] == "block" else hs.DIST_BLOCK_CYCLIC
+        p = hs.Plan(c["n"], c["P"], c["Q"], c["G"], c["b"], c["M"], m=c["m"], k=c["k"], dist=d,
+                    nb=c["nb"], prec=c["prec"], persistent=c["persistent"])
+        ws = p.workspace()
+        ws.fill_(0x3C)
+        p.prepare_workspace(ws)
+        torch.cuda.synchronize()
+        nit = p.num_items
+        got = ws[:16 * nit].view(torch.int32).cpu().numpy().reshape(nit, 4)
+        assert np.array_equal(got, p.work_items()), c
+        p.close()
+
+    _say("case random device tables")
+    check()
