@@ -135,3 +135,39 @@ def test_lookahead_plan_reused_and_split_form():
     bound = core.gamma(n) * s + 2 * core.U * np.abs(A[rows, cols]) + (n // 256) * 1e-14 * s
     assert np.all(r <= bound)
     torch.cuda.synchronize()
+
+
+def test_random_lu_plans():
+    # random sizes, block sizes, grids, groupings and schedules (hypothesis):
+    # integer factors with power-of-two pivots come back bit for bit, and a
+    # diagonally dominant matrix's factors meet the backward-error bound on
+    # every entry
+    from hypothesis import given, settings, strategies as st, HealthCheck
+
+    @st.composite
+    def cases(draw):
+        n = draw(st.integers(1, 300))
+        b = draw(st.integers(1, 64))
+        M = b * draw(st.integers(1, 4))
+        P = draw(st.integers(1, 4))
+        Q = draw(st.integers(1, 4))
+        G = draw(st.sampled_from(sorted({I * J for I in range(1, P + 1) if P % I == 0
+                                         for J in range(1, Q + 1) if Q % J == 0})))
+        return n, P, Q, G, b, M, draw(st.integers(0, 1)), draw(st.integers(0, 10 ** 6))
+
+    @settings(max_examples=50, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+    @given(cases())
+    def check(c):
+        n, P, Q, G, b, M, la, seed = c
+        _say("case random lu %r" % (c,))
+        L0, U0 = _integer_factors(n, seed)
+        L, U = lu_ref.unpack(_factor(L0 @ U0, P, Q, G, b, M, lookahead=la))
+        assert np.array_equal(L, L0) and np.array_equal(U, U0)
+        A = _dominant(n, seed + 1)
+        LU = _factor(A, P, Q, G, b, M, lookahead=la)
+        rows, cols = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        rows, cols = rows.ravel(), cols.ravel()
+        r, s = lu_ref.residual_sampled(LU, A, rows, cols)
+        assert np.all(r <= core.gamma(n) * s + 2 * core.U * np.abs(A[rows, cols]))
+
+    check()
