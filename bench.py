@@ -171,6 +171,8 @@ def gpu_uniform(shape, seed):
 def run_plan(hs, plan, dA, dB, dC, ws, stream, args):
     run = lambda: plan.run(dA, dB, dC, ws=ws, stream=stream)
     import torch
+    # the operands and the workspace come from the default stream
+    stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             run()
@@ -184,6 +186,7 @@ def product_launch_ms(plan, g, dA, dB, ws, stream, args):
     import torch
     C2 = torch.empty((plan.m, plan.n), dtype=torch.float64, device="cuda")
     prod = lambda: plan.outer_products(g, dA, dB, C2, ws, stream=stream)
+    stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
         for _ in range(3):
             prod()
@@ -281,6 +284,7 @@ def bench_workloads(names, args, stream):
                 times = []
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
+                stream.wait_stream(torch.cuda.current_stream())   # A0 and ws are ready
                 for rep in range(args.warmup + args.steps):
                     with torch.cuda.stream(stream):
                         dA.copy_(A0)
@@ -338,8 +342,11 @@ def main():
                 B = inputs.uniform(n, n, inputs.SEED_B)
             dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
             ref = hs.Plan(n, P, Q, G, b, M)
-            ref.run(dA, dB, dC, ws=ref.workspace(), stream=stream)
+            ref_ws = ref.workspace()
+            stream.wait_stream(torch.cuda.current_stream())
+            ref.run(dA, dB, dC, ws=ref_ws, stream=stream)
             torch.cuda.synchronize()
+            del ref_ws
             c64 = dC.cpu().numpy()[rows, cols]
             operand_sets[sigma] = (A, B, dA, dB, c64, sampled_scale(dA, dB, rows, cols))
         return operand_sets[sigma]

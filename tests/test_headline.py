@@ -74,6 +74,7 @@ def _run(w, prec, M):
     C = torch.empty((N, N), dtype=torch.float64, device="cuda")
     C.fill_(float("nan"))
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())  # after the NaN fill
     with torch.cuda.stream(stream):
         plan.run(w["dA"], w["dB"], C, ws=ws, stream=stream)
     stream.synchronize()

@@ -347,6 +347,7 @@ def test_c3_block_cyclic_split_graph(prec):
     stream = torch.cuda.Stream()
     outs = []
     for rep in range(3):
+        stream.wait_stream(torch.cuda.current_stream())  # after the eager work
         with torch.cuda.stream(stream):
             C.fill_(float("nan"))
             ws.fill_(0xA5)  # the graph regenerates the work-item table on each replay

@@ -73,3 +73,41 @@ def test_random_splits_meet_gate(c, prec, sigma, seed):
     with np.errstate(divide="ignore", invalid="ignore"):
         sc = np.where(s > 0, np.abs(got - ref) / s, np.abs(got - ref))
     assert float(sc.max()) <= GATE, "max scaled err %g" % float(sc.max())
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(plans(), st.integers(0, 2 ** 31 - 1))
+def test_random_graph_replays_equal_direct_launches(c, seed):
+    # hsumma_run captured in a HIP graph (the work-item table regenerated on
+    # every replay) against the direct launches, bit for bit, with eager work
+    # and a dirtied workspace between replays
+    import torch
+    print("case random graph %r" % (c,), flush=True)
+    d = hs.DIST_BLOCK if c["dist"] == "block" else hs.DIST_BLOCK_CYCLIC
+    kw = dict(m=c["m"], k=c["k"], dist=d, nb=c["nb"], prec=c["prec"],
+              persistent=c["persistent"])
+    A = dev(inputs.uniform(c["m"], c["k"], seed))
+    B = dev(inputs.uniform(c["k"], c["n"], seed + 1))
+    direct = hs.Plan(c["n"], c["P"], c["Q"], c["G"], c["b"], c["M"], **kw)
+    ref = torch.empty((c["m"], c["n"]), dtype=torch.float64, device="cuda")
+    ws_direct = direct.workspace()
+    direct.run(A, B, ref, ws=ws_direct)
+    graph = hs.Plan(c["n"], c["P"], c["Q"], c["G"], c["b"], c["M"], use_graph=1, **kw)
+    ws = graph.workspace()
+    stream = torch.cuda.Stream()
+    C = torch.empty_like(ref)
+    for rep in range(3):
+        # the side stream starts after everything queued on the default
+        # stream (the direct run, the eager add): memory the caching
+        # allocator hands out there may still be in use by that work
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            C.fill_(float("nan"))
+            ws.fill_(0x5A + rep)
+            graph.run(A, B, C, ws=ws, stream=stream)
+        stream.synchronize()
+        assert torch.equal(C, ref)
+        A.add_(0.0)
+    torch.cuda.synchronize()
+    direct.close()
+    graph.close()

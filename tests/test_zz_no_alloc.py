@@ -41,3 +41,30 @@ def test_noalloc_equals_run(prec):
         assert torch.equal(C, ref)
         assert np.isfinite(C.cpu().numpy()).all()
         p.close()
+
+
+def test_noalloc_equals_run_random_plans():
+    # random plans (the strategy of tests/test_items_random.py), run back to
+    # back through the one shared scratch array
+    import torch
+    from hypothesis import given, settings, strategies as st, HealthCheck
+    from test_items_random import plans
+
+    @settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+    @given(plans(), st.integers(0, 2 ** 31 - 1))
+    def check(c, seed):
+        d = hs.DIST_BLOCK if c["dist"] == "block" else hs.DIST_BLOCK_CYCLIC
+        p = hs.Plan(c["n"], c["P"], c["Q"], c["G"], c["b"], c["M"], m=c["m"], k=c["k"], dist=d,
+                    nb=c["nb"], prec=c["prec"], persistent=c["persistent"])
+        A = dev(inputs.uniform(c["m"], c["k"], seed))
+        B = dev(inputs.uniform(c["k"], c["n"], seed + 1))
+        ref = torch.empty((c["m"], c["n"]), dtype=torch.float64, device="cuda")
+        p.run(A, B, ref, ws=p.workspace())
+        C = torch.full_like(ref, float("nan"))
+        p.run_noalloc(A, B, C)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), c
+        p.close()
+
+    print("case noalloc random plans", flush=True)
+    check()
