@@ -26,9 +26,10 @@ workload.
 dominant kernel: c1 (n = 8192, 8 x 8 grid, G = 4, M = 256, b = 64, FP64),
 c3 (n = 10000 on a 6 x 10 block-cyclic grid, b = M = 128, one grouped
 persistent launch per step over the 60 uneven tiles, replayed as a HIP
-graph; FP64 and the INT8 split) and lu (n = 16384 LU without pivoting,
-16 x 16 grid, G = 16, b = 64, M = 1024: the trailing updates are HSUMMA
-outer updates).
+graph; FP64 and the INT8 split), lu (n = 16384 LU without pivoting,
+16 x 16 grid, G = 16: the trailing updates are HSUMMA outer updates) and la
+(the split forms with and without look-ahead, m = n = 1024, k = 65536,
+where one product launch fills half the CUs).
 
 `roofline` describes the dominant kernel of the reported path: its
 algorithmic flops per launch over its average launch duration, measured with
@@ -76,7 +77,7 @@ def parse():
     ap.add_argument("--M", type=int, default=1024)
     ap.add_argument("--sigma", type=float, default=2.0)
     ap.add_argument("--paths", type=str, default="fp64,bf16,int8,fp8,bf16_uniform,int8_uniform")
-    ap.add_argument("--workloads", type=str, default="c1,c3,lu")
+    ap.add_argument("--workloads", type=str, default="c1,c3,lu,la")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--samples", type=int, default=512)
@@ -268,6 +269,41 @@ def bench_workloads(names, args, stream):
                 out[name] = rec
                 log("%s: %.3f ms/step, %.1f GFLOP/s" % (name, ms, rec["gflops"]))
                 del plan, ws
+            del dA, dB, dC
+        elif wl == "la":
+            # the split forms' look-ahead where the product launch leaves CUs
+            # idle: C of 1024 x 1024 is 128 macro-tiles of 64 x 128 for 256 CUs
+            from paper_1306_4161_amd import inputs
+            m = n = 1024
+            k, P, Q, G, b, M = 65536, 4, 4, 4, 256, 1024
+            A = inputs.exponent_spread(m, k, 2013, args.sigma)
+            B = inputs.exponent_spread(k, n, 4161, args.sigma)
+            dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            del A, B
+            dC = torch.empty((m, n), dtype=torch.float64, device="cuda")
+            flops = 2.0 * m * n * k
+            for prec, name in ((hs.SPLIT_INT8, "la_int8"), (hs.SPLIT_BF16, "la_bf16")):
+                rec = {"workload": "m = n = 1024, k = 65536, 4x4 grid, G=4, b=256, M=1024, "
+                                   "sigma=%g: the split of panel g + 1 on a second stream "
+                                   "while the products of panel g run" % args.sigma}
+                outs = []
+                for la in (0, 1):
+                    plan = hs.Plan(n, P, Q, G, b, M, m=m, k=k, prec=prec, lookahead=la)
+                    ws = plan.workspace()
+                    ms = run_plan(hs, plan, dA, dB, dC, ws, stream, args)
+                    key = "lookahead" if la else "plain"
+                    rec[key] = {"ms_per_step": round(ms, 3),
+                                "ms_per_step_median": round(LAST_MEDIAN_MS[0], 3),
+                                "gflops": round(flops / (ms * 1e-3) / 1e9, 1)}
+                    outs.append(dC.clone())
+                    plan.close()
+                    del plan, ws
+                rec["speedup"] = round(rec["plain"]["ms_per_step"] / rec["lookahead"]["ms_per_step"], 3)
+                rec["bitwise_equal"] = bool(torch.equal(outs[0], outs[1]))
+                out[name] = rec
+                log("%s: plain %.3f ms, look-ahead %.3f ms" % (
+                    name, rec["plain"]["ms_per_step"], rec["lookahead"]["ms_per_step"]))
+                del outs
             del dA, dB, dC
         elif wl == "lu":
             n, P, Q, G = 16384, 16, 16, 16

@@ -112,7 +112,12 @@ typedef struct {
   int32_t waves;      /* FP64 path: waves per workgroup of the macro-tile's     */
                       /* kernel; 0 => the tile's first compiled configuration   */
   int32_t lookahead;  /* hsumma_lu: 1 = factor the next panel while the rest of */
-                      /* the trailing update runs on a second stream            */
+                      /* the trailing update runs on a second stream.  Split    */
+                      /* forms: 1 = hsumma_run splits outer panel g + 1 on a    */
+                      /* second stream while the products of panel g run (the   */
+                      /* workspace holds two sets of digit planes; panel g uses */
+                      /* set g % 2 in every call).  Same result, bit for bit.   */
+                      /* No effect on the FP64 path                             */
   int32_t wgs_per_cu; /* persistent launches: workgroups per CU, at most what   */
                       /* fits; 0 => what fits.  Fewer leave room on every CU    */
                       /* for concurrent work (hsumma_lu's look-ahead)           */
@@ -216,7 +221,8 @@ int hsumma_outer_update(hsumma_plan_t plan, int64_t outer,
 /*
  * Split forms only: the slice-product launch of outer step g alone, on the
  * digit planes the workspace holds from a previous call that split that
- * outer step's panel (C += its product); a panel that split sent to the
+ * outer step's panel (C += its product; with look-ahead, set g % 2 of the
+ * planes); a panel that split sent to the
  * FP64 kernel (slice count 0) is recomputed by it from A and B.  Lets a
  * caller time or repeat the matrix-core part without the split.
  */
@@ -230,7 +236,12 @@ int hsumma_outer_products(hsumma_plan_t plan, int64_t outer, const double* A, in
  * done): every outer step in order, the first one storing instead of
  * accumulating, so C needs no clearing.  With
  * opts.use_graph the launch sequence (work-item table included) is captured
- * once per (pointers, stream, device) and replayed.
+ * once per (pointers, stream, device) and replayed.  With opts.lookahead (a
+ * split form, more than one outer step) the split of each next panel runs
+ * on a stream the plan creates on its first such call (Sec. VI: the next
+ * step's panel work overlaps this step's update); events order it, and the
+ * call's work all ends on `stream`.  Such a plan then serves one device, and
+ * its calls are serialised on the host (they share that stream).
  */
 int hsumma_run(hsumma_plan_t plan, const double* A, int64_t lda, const double* B,
                int64_t ldb, double* C, int64_t ldc, void* ws, size_t ws_bytes,

@@ -89,6 +89,13 @@ struct hsumma_plan_s {
   int32_t Wp = 0;              // padded panel width
   size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_stats = 0, off_slices = 0,
          off_dump = 0, ws_bytes = 0;
+  // split forms with look-ahead: a second set of digit planes and exponents
+  // (panel g uses set g % 2), the second stream and its events
+  bool lookahead = false;
+  size_t off_digA1 = 0, off_digB1 = 0, off_eA1 = 0, off_fB1 = 0;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_start = nullptr, ev_split = nullptr, ev_prod = nullptr;
+  int adevice = -1;
   std::mutex mu;
   bool have_graph = false;
   GraphKey gkey{};
@@ -329,28 +336,12 @@ int launch_fp64_range(hsumma_plan_t p, const hs::TileCfg& cfg, const double* A, 
   return HSUMMA_OK;
 }
 
-// Launch the local update over k-range [k0, k1) (starting at an inner-step
-// boundary) for every work item; the table must already be in `ws`.  `slot`
-// indexes the per-panel statistics of the precision form.
-int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
-                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init, int64_t slot,
-                 void* ws, hipStream_t stream, bool products_only = false) {
-  if (p->items.empty()) return HSUMMA_OK;
-  if (p->fmt < 0)
-    return launch_fp64_range(p, p->cfg, A, lda, B, ldb, C, ldc, k0, k1, zero_init,
-                             p->opts.persistent != 0, nullptr, ws, stream);
-  // ---- precision form: split the panel, then slice products ----------------
+// The split of the panel k-range [k0, k1) of a precision form: its digit
+// planes and exponents go to set `buf` of the workspace (set 1 exists with
+// look-ahead only), its statistics and slice count to slot `slot`.
+hs::SplitArgs split_args(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
+                         int64_t ldb, int64_t k0, int64_t k1, int64_t slot, int buf, void* ws) {
   uint8_t* w8 = (uint8_t*)ws;
-  uint32_t* stats = (uint32_t*)(w8 + p->off_stats) + hs::kStatWords * slot;
-  int32_t* slices = (int32_t*)(w8 + p->off_slices) + slot;
-  hipError_t e = hipSuccess;
-  if (!products_only) {
-    e = hs::launch_zero_u32(stats, hs::kStatWords, stream);
-    if (e != hipSuccess) {
-      set_error(std::string("stats clear: ") + hipGetErrorString(e));
-      return HSUMMA_ERR_DEVICE;
-    }
-  }
   hs::SplitArgs sa;
   sa.A = A; sa.lda = lda; sa.B = B; sa.ldb = ldb;
   sa.m = (int32_t)p->m; sa.n = (int32_t)p->n; sa.k0 = (int32_t)k0; sa.w = (int32_t)(k1 - k0);
@@ -361,18 +352,36 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   sa.fixed_s = p->opts.slices; sa.smin = p->opts.min_slices; sa.tau_bits = p->opts.tau_bits;
   sa.log2k = (float)std::log2((double)std::max<int64_t>(1, p->k));
   sa.log2w = (float)std::log2((double)std::max<int64_t>(1, k1 - k0));
-  sa.digA = w8 + p->off_digA; sa.planeA = (int64_t)p->m * sa.Wp;
-  sa.digB = w8 + p->off_digB; sa.planeB = (int64_t)p->n * sa.Wp;
-  sa.eA = (int32_t*)(w8 + p->off_eA); sa.fB = (int32_t*)(w8 + p->off_fB);
-  sa.stats = stats;
-  sa.slices_out = slices;
-  if (!products_only) {
-    e = hs::launch_split(sa, stream);
-    if (e != hipSuccess) {
-      set_error(std::string("split launch: ") + hipGetErrorString(e));
-      return HSUMMA_ERR_DEVICE;
-    }
+  sa.digA = w8 + (buf ? p->off_digA1 : p->off_digA); sa.planeA = (int64_t)p->m * sa.Wp;
+  sa.digB = w8 + (buf ? p->off_digB1 : p->off_digB); sa.planeB = (int64_t)p->n * sa.Wp;
+  sa.eA = (int32_t*)(w8 + (buf ? p->off_eA1 : p->off_eA));
+  sa.fB = (int32_t*)(w8 + (buf ? p->off_fB1 : p->off_fB));
+  sa.stats = (uint32_t*)(w8 + p->off_stats) + hs::kStatWords * slot;
+  sa.slices_out = (int32_t*)(w8 + p->off_slices) + slot;
+  return sa;
+}
+
+// The panel pass of a precision form: clear the panel's statistics, then
+// the statistics and digit kernels.
+int launch_panel_split(const hs::SplitArgs& sa, hipStream_t stream) {
+  hipError_t e = hs::launch_zero_u32(sa.stats, hs::kStatWords, stream);
+  if (e != hipSuccess) {
+    set_error(std::string("stats clear: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
   }
+  e = hs::launch_split(sa, stream);
+  if (e != hipSuccess) {
+    set_error(std::string("split launch: ") + hipGetErrorString(e));
+    return HSUMMA_ERR_DEVICE;
+  }
+  return HSUMMA_OK;
+}
+
+// The product pass of a precision form over the panel split into `sa`: the
+// slice products of every work item, then the FP64 route.
+int launch_panel_products(hsumma_plan_t p, const hs::SplitArgs& sa, double* C, int64_t ldc,
+                          int64_t k0, int64_t k1, int zero_init, void* ws, hipStream_t stream) {
+  uint8_t* w8 = (uint8_t*)ws;
   int grid = 0;
   int rc = launch_grid(p, true, 1, &grid);
   if (rc) return rc;
@@ -385,14 +394,14 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
     la.bytesB = (uint32_t)(p->opts.max_slices * sa.planeB * esz);
   }
   la.eA = sa.eA; la.fB = sa.fB;
-  la.slices = slices;
+  la.slices = sa.slices_out;
   la.C = C; la.ldc = ldc;
   la.items = (const hs::WorkItem*)(w8 + p->off_items);
   la.nitems = (int32_t)p->items.size(); la.per_xcd = p->per_xcd;
   la.Wp = sa.Wp; la.nchunks = sa.Wp / hs::kSplitChunk;
   la.zero_init = zero_init; la.persistent = 1;
   la.dump = (double*)(w8 + p->off_dump);
-  e = hs::launch_slices(p->fmt, la, grid, stream);
+  hipError_t e = hs::launch_slices(p->fmt, la, grid, stream);
   if (e != hipSuccess) {
     set_error(std::string("slice products launch: ") + hipGetErrorString(e));
     return HSUMMA_ERR_DEVICE;
@@ -402,8 +411,59 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   // the FP64 kernel instead, on the same items; the decision is on the device
   // (slice count 0), so both launches are always issued and exactly one of
   // them does work.
-  return launch_fp64_range(p, hs::TileCfg{64, 128, 16}, A, lda, B, ldb, C, ldc, k0, k1,
-                           zero_init, true, slices, ws, stream);
+  return launch_fp64_range(p, hs::TileCfg{64, 128, 16}, sa.A, sa.lda, sa.B, sa.ldb, C, ldc, k0,
+                           k1, zero_init, true, sa.slices_out, ws, stream);
+}
+
+// Launch the local update over k-range [k0, k1) (starting at an inner-step
+// boundary) for every work item; the table must already be in `ws`.  `slot`
+// indexes the per-panel statistics of the precision form.
+int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double* C, int64_t ldc, int64_t k0, int64_t k1, int zero_init, int64_t slot,
+                 void* ws, hipStream_t stream, bool products_only = false) {
+  if (p->items.empty()) return HSUMMA_OK;
+  if (p->fmt < 0)
+    return launch_fp64_range(p, p->cfg, A, lda, B, ldb, C, ldc, k0, k1, zero_init,
+                             p->opts.persistent != 0, nullptr, ws, stream);
+  // a look-ahead plan keeps outer panel g's planes in set g % 2 in every call
+  const int buf = p->lookahead ? (int)(slot & 1) : 0;
+  const hs::SplitArgs sa = split_args(p, A, lda, B, ldb, k0, k1, slot, buf, ws);
+  if (!products_only) {
+    int rc = launch_panel_split(sa, stream);
+    if (rc) return rc;
+  }
+  return launch_panel_products(p, sa, C, ldc, k0, k1, zero_init, ws, stream);
+}
+
+bool uses_lookahead(hsumma_plan_t p) { return p->lookahead && p->outer_lo.size() > 2; }
+
+// The second stream and the events of a look-ahead plan, made on first use
+// (the caller holds the plan's mutex); the plan then stays on that device.
+int ensure_aux(hsumma_plan_t p) {
+  int dev = 0;
+  HS_CHECK_HIP(hipGetDevice(&dev));
+  if (p->aux) {
+    if (p->adevice != dev) return invalid("a plan with look-ahead is used on one device only");
+    return HSUMMA_OK;
+  }
+  hipStream_t st = nullptr;
+  HS_CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < 3; ++i) {
+    const hipError_t e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      (void)hipStreamDestroy(st);
+      set_error(std::string("look-ahead event: ") + hipGetErrorString(e));
+      return HSUMMA_ERR_DEVICE;
+    }
+  }
+  p->aux = st;
+  p->ev_start = ev[0];
+  p->ev_split = ev[1];
+  p->ev_prod = ev[2];
+  p->adevice = dev;
+  return HSUMMA_OK;
 }
 
 // A named range per outer step (host side: it brackets the launches, which
@@ -417,10 +477,54 @@ struct StepRange {
   ~StepRange() { roctxRangePop(); }
 };
 
+// The whole product of a split form with look-ahead (Sec. VI: the next
+// step's panel work overlaps this step's update).  The split of panel g + 1
+// runs on the plan's second stream, into the other digit-plane set, while
+// the products of panel g run on the caller's stream.  Events order each
+// split after the product pass that last read its set (panel g - 1) and
+// each product pass after its split; every split is waited for by the
+// caller's stream, so the call's work all ends there.  The kernels and
+// their inputs are those of the plain sequence: the result is the same, bit
+// for bit.
+int run_lookahead(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double* C, int64_t ldc, void* ws, hipStream_t s) {
+  int rc = prepare_items(p, ws, s);
+  if (rc) return rc;
+  const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
+  const int64_t* lo = p->outer_lo.data();
+  HS_CHECK_HIP(hipEventRecord(p->ev_start, s));
+  rc = launch_panel_split(split_args(p, A, lda, B, ldb, lo[0], lo[1], 0, 0, ws), s);
+  if (rc) return rc;
+  bool pending = false;   // a split on the second stream not yet waited for
+  for (int64_t g = 0; g < nouter && !rc; ++g) {
+    StepRange range(g);
+    if (pending) {
+      HS_CHECK_HIP(hipStreamWaitEvent(s, p->ev_split, 0));
+      pending = false;
+    }
+    if (g + 1 < nouter) {
+      HS_CHECK_HIP(hipStreamWaitEvent(p->aux, g == 0 ? p->ev_start : p->ev_prod, 0));
+      rc = launch_panel_split(
+          split_args(p, A, lda, B, ldb, lo[g + 1], lo[g + 2], g + 1, (int)((g + 1) & 1), ws),
+          p->aux);
+      HS_CHECK_HIP(hipEventRecord(p->ev_split, p->aux));
+      pending = true;
+      if (rc) break;
+    }
+    rc = launch_panel_products(p, split_args(p, A, lda, B, ldb, lo[g], lo[g + 1], g, (int)(g & 1), ws),
+                               C, ldc, lo[g], lo[g + 1], g == 0 ? 1 : 0, ws, s);
+    if (!rc) HS_CHECK_HIP(hipEventRecord(p->ev_prod, s));
+  }
+  // after an error too: nothing of this call stays on the second stream alone
+  if (pending) HS_CHECK_HIP(hipStreamWaitEvent(s, p->ev_split, 0));
+  return rc;
+}
+
 // The whole product: the work-item table, then every outer step in order
 // (the first stores instead of accumulating).
 int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
                double* C, int64_t ldc, void* ws, hipStream_t stream) {
+  if (uses_lookahead(p)) return run_lookahead(p, A, lda, B, ldb, C, ldc, ws, stream);
   int rc = prepare_items(p, ws, stream);
   if (rc) return rc;
   const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
@@ -433,14 +537,31 @@ int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, i
   return HSUMMA_OK;
 }
 
+// run_direct for a caller's call: a look-ahead plan's second stream and
+// events are shared by the plan's calls, so those calls are serialised.
+int run_direct_call(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, void* ws, hipStream_t s) {
+  if (!uses_lookahead(p)) return run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+  std::lock_guard<std::mutex> lk(p->mu);
+  int rc = ensure_aux(p);
+  if (rc) return rc;
+  return run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+}
+
 // Whole product on an explicit workspace, direct or through the plan's graph.
 int run_on(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
            double* C, int64_t ldc, void* ws, hipStream_t s) {
-  if (!p->opts.use_graph || s == nullptr) return run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+  if (!p->opts.use_graph || s == nullptr) return run_direct_call(p, A, lda, B, ldb, C, ldc, ws, s);
 
   // Graph mode: capture the launch sequence (table generation included)
-  // once per (pointers, stream, device) and replay it.
+  // once per (pointers, stream, device) and replay it.  With look-ahead the
+  // second stream joins the capture through the events and is joined back
+  // before it ends.
   std::lock_guard<std::mutex> lk(p->mu);
+  if (uses_lookahead(p)) {
+    int rc = ensure_aux(p);   // outside the capture
+    if (rc) return rc;
+  }
   int dev = 0;
   HS_CHECK_HIP(hipGetDevice(&dev));
   GraphKey key{A, lda, B, ldb, C, ldc, ws, (void*)s};
@@ -671,6 +792,13 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     p->off_stats = off; off = al(off + nout * hs::kStatWords * 4);
     p->off_slices = off; off = al(off + nout * 4);
     p->off_dump = off; off = al(off + 64 * sizeof(double));
+    if (o.lookahead) {
+      p->lookahead = true;
+      p->off_digA1 = off; off = al(off + sl * (size_t)m * Wp * esz);
+      p->off_digB1 = off; off = al(off + sl * (size_t)n * Wp * esz);
+      p->off_eA1 = off; off = al(off + (size_t)m * 4);
+      p->off_fB1 = off; off = al(off + (size_t)n * 4);
+    }
   }
   p->ws_bytes = std::max<size_t>(off, 256);
   *out = p;
@@ -685,6 +813,19 @@ void hsumma_plan_destroy(hsumma_plan_t p) {
     if (p->gdevice >= 0 && p->gdevice != cur) hipSetDevice(p->gdevice);
     hipGraphExecDestroy(p->gexec);
     if (cur >= 0 && p->gdevice != cur) hipSetDevice(cur);
+  }
+  if (p->aux) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+    if (p->adevice >= 0 && p->adevice != cur) hipSetDevice(p->adevice);
+    // the calls that used the second stream joined it into their own
+    // stream; its last work must still end before the stream goes
+    (void)hipStreamSynchronize(p->aux);
+    (void)hipEventDestroy(p->ev_start);
+    (void)hipEventDestroy(p->ev_split);
+    (void)hipEventDestroy(p->ev_prod);
+    (void)hipStreamDestroy(p->aux);
+    if (cur >= 0 && p->adevice != cur) hipSetDevice(cur);
   }
   delete p;
 }
@@ -828,7 +969,7 @@ int hsumma_run_noalloc(hsumma_plan_t p, const double* A, int64_t lda, const doub
   }
   void* ws = nullptr;
   if ((rc = scratch_address(&ws))) return rc;
-  return run_direct(p, A, lda, B, ldb, C, ldc, ws, (hipStream_t)stream);
+  return run_direct_call(p, A, lda, B, ldb, C, ldc, ws, (hipStream_t)stream);
 }
 
 size_t hsumma_noalloc_max_workspace(void) { return kScratchBytes; }

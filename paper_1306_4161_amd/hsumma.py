@@ -177,7 +177,7 @@ class Plan:
     def __init__(self, n, P, Q, G, b, M=None, *, m=0, k=0, dist=DIST_BLOCK, nb=0,
                  prec=FP64, slices=0, min_slices=0, max_slices=0, tile_m=0, tile_n=0,
                  kc=0, persistent=0, use_graph=0, tau_bits=0, staged=0, waves=0,
-                 wgs_per_cu=0):
+                 wgs_per_cu=0, lookahead=0):
         L = lib()
         o = Opts()
         L.hsumma_opts_default(ctypes.byref(o))
@@ -185,7 +185,7 @@ class Plan:
         o.slices, o.min_slices, o.max_slices = slices, min_slices, max_slices
         o.tile_m, o.tile_n, o.kc = tile_m, tile_n, kc
         o.persistent, o.use_graph, o.tau_bits, o.staged = persistent, use_graph, tau_bits, staged
-        o.waves, o.wgs_per_cu = waves, wgs_per_cu
+        o.waves, o.wgs_per_cu, o.lookahead = waves, wgs_per_cu, lookahead
         h = ctypes.c_void_p()
         _check(L.hsumma_plan(ctypes.byref(h), n, P, Q, G, b, M if M is not None else b,
                              ctypes.byref(o)))

@@ -254,6 +254,25 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch_array():
     big.close()
 
 
+def test_split_lookahead_doubles_the_panel_sets():
+    # look-ahead in a split form: a second set of digit planes (max_slices
+    # planes of m x Wp and n x Wp digits) and exponents; nothing for FP64
+    al = lambda x: (x + 255) // 256 * 256
+    for prec, esz, planes in ((hs.SPLIT_BF16, 2, 7), (hs.SPLIT_INT8, 1, 8)):
+        m, n, k, M = 600, 520, 1000, 128
+        plain = hs.Plan(n, 2, 2, 4, 32, M, m=m, k=k, prec=prec)
+        ahead = hs.Plan(n, 2, 2, 4, 32, M, m=m, k=k, prec=prec, lookahead=1)
+        Wp = 128
+        extra = (al(planes * m * Wp * esz) + al(planes * n * Wp * esz) + al(4 * m) + al(4 * n))
+        assert ahead.workspace_size == plain.workspace_size + extra
+        assert ahead.work_items().tolist() == plain.work_items().tolist()
+        plain.close(); ahead.close()
+    f0 = hs.Plan(512, 2, 2, 4, 32, 128)
+    f1 = hs.Plan(512, 2, 2, 4, 32, 128, lookahead=1)
+    assert f1.workspace_size == f0.workspace_size
+    f0.close(); f1.close()
+
+
 def test_lu_plans_validate_and_size_their_workspace():
     with pytest.raises(hs.HsummaError):
         hs.LuPlan(256, 1, 1, 1, 128, 128)            # b beyond the 64 of the panel kernels
