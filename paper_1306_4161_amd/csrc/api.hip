@@ -87,12 +87,12 @@ struct hsumma_plan_s {
   size_t off_items = 0, off_items_tmp = 0;
   int32_t fmt = -1;            // -1: FP64 path; 0: BF16, 1: FP8-e4m3, 2: INT8 digits
   int32_t Wp = 0;              // padded panel width
-  size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_stats = 0, off_slices = 0,
-         off_dump = 0, ws_bytes = 0;
+  size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_part = 0, off_stats = 0,
+         off_slices = 0, off_dump = 0, ws_bytes = 0;
   // split forms with look-ahead: a second set of digit planes and exponents
   // (panel g uses set g % 2), the second stream and its events
   bool lookahead = false;
-  size_t off_digA1 = 0, off_digB1 = 0, off_eA1 = 0, off_fB1 = 0;
+  size_t off_digA1 = 0, off_digB1 = 0, off_eA1 = 0, off_fB1 = 0, off_part1 = 0;
   hipStream_t aux = nullptr;
   hipEvent_t ev_start = nullptr, ev_split = nullptr, ev_prod = nullptr;
   int adevice = -1;
@@ -356,6 +356,8 @@ hs::SplitArgs split_args(hsumma_plan_t p, const double* A, int64_t lda, const do
   sa.digB = w8 + (buf ? p->off_digB1 : p->off_digB); sa.planeB = (int64_t)p->n * sa.Wp;
   sa.eA = (int32_t*)(w8 + (buf ? p->off_eA1 : p->off_eA));
   sa.fB = (int32_t*)(w8 + (buf ? p->off_fB1 : p->off_fB));
+  sa.part = (double*)(w8 + (buf ? p->off_part1 : p->off_part));
+  sa.nslab = (sa.Wp + 63) / 64;
   sa.stats = (uint32_t*)(w8 + p->off_stats) + hs::kStatWords * slot;
   sa.slices_out = (int32_t*)(w8 + p->off_slices) + slot;
   return sa;
@@ -775,7 +777,9 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
   }
   // Workspace layout: the work-item table (and, for the longest-first order,
   // its unordered copy), then the precision form's digit planes, exponents,
-  // per-panel statistics and slice counts, and the INT8 kernel's dump area.
+  // per-slab partial statistics, per-panel statistics and slice counts, and
+  // the INT8 kernel's dump area (with look-ahead, a second set of planes,
+  // exponents and partial statistics after it).
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t off = 0;
   const size_t nit = p->items.size();
@@ -789,6 +793,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     p->off_digB = off; off = al(off + sl * (size_t)n * Wp * esz);
     p->off_eA = off; off = al(off + (size_t)m * 4);
     p->off_fB = off; off = al(off + (size_t)n * 4);
+    p->off_part = off; off = al(off + (size_t)hs::split_part_doubles(m, n, p->Wp) * 8);
     p->off_stats = off; off = al(off + nout * hs::kStatWords * 4);
     p->off_slices = off; off = al(off + nout * 4);
     p->off_dump = off; off = al(off + 64 * sizeof(double));
@@ -798,6 +803,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
       p->off_digB1 = off; off = al(off + sl * (size_t)n * Wp * esz);
       p->off_eA1 = off; off = al(off + (size_t)m * 4);
       p->off_fB1 = off; off = al(off + (size_t)n * 4);
+      p->off_part1 = off; off = al(off + (size_t)hs::split_part_doubles(m, n, p->Wp) * 8);
     }
   }
   p->ws_bytes = std::max<size_t>(off, 256);

@@ -198,348 +198,206 @@ __device__ __forceinline__ float coherence(double rs, double ra) {
   return ra > 0.0 ? (float)(fabs(rs) / ra) : 0.0f;
 }
 
-// ---- split: statistics pass, then digit pass; 64 lines per block ------------
-// A line is a row of A or a column of B.  Lane = line, wave w = the 16-k
-// blocks w, w + 8, w + 16, ...  The digits of a (line, k16 block) unit are 16
-// consecutive elements of one plane (32 bytes in BF16), and consecutive
-// lines are consecutive units of the k16-block-major layout, so each wave
-// stores 64 x 32 contiguous bytes per plane.  A rows are read as 8 rows x
-// 128 bytes per wave-load (staged through LDS in the digit pass); B columns
-// one 512-byte row segment per wave-load.  Every wave issues the loads of its
-// next 16-k tile before it works on the current one.  The statistics pass
-// writes each line's exponent and the panel's kappa; the digit pass then
-// knows the panel's slice count and writes only those planes.  Both passes
-// run over A's and B's blocks in one launch each.
-template <bool COLS>
-__device__ __forceinline__ double panel_at(const SplitArgs& p, int ln, int kk) {
-  return COLS ? p.B[(int64_t)(p.k0 + kk) * p.ldb + ln] : p.A[(int64_t)ln * p.lda + p.k0 + kk];
-}
+// ---- split: statistics, their combination, digits ---------------------------
+// A line is a row of A or a column of B (line index: A rows 0 .. m-1, then
+// B columns m .. m+n-1).  The panel is cut into blocks of 64 lines x one
+// 64-k slab, 4 waves each: wave w owns the 16-k tile [64 slab + 16 w, + 16),
+// one line per lane, with no loop, so that many blocks are in flight per CU
+// and narrow problems (few lines, a wide panel) still fill the chip.  A rows
+// are staged through a per-wave LDS tile, read as 8 rows x 128 bytes per
+// wave-load and then one row per lane (row stride 18 doubles: the 16-byte
+// reads of 16 lanes hit distinct banks); B columns are read directly, one
+// 512-byte row segment per wave-load.
+//   1. statistics: each line's partial sums over the slab (max |x|, sum |x|,
+//      the coherence sums, the log-magnitude sum and count) go to the
+//      workspace, field-major, slab by slab;
+//   2. combination: one thread per line adds its partials in slab order (so
+//      the result does not depend on scheduling), writes the line's
+//      exponent and folds the line into the panel's statistics;
+//   3. digits: the panel's slice count from its statistics, then the digit
+//      planes of each tile (only those planes).
+constexpr int kSplitWaves = 4;               // waves per block
+constexpr int kSlabK = 16 * kSplitWaves;     // k per block
+constexpr int kTileStride = 18;              // doubles per staged row
+constexpr int kPartFields = 6;               // partial sums per line and slab
 
-constexpr int kSplitWaves = 8;                // waves per block of 64 lines
-
-template <bool COLS>
-__device__ void split_stats_lines(const SplitArgs& p, int blk) {
-  constexpr int NW = kSplitWaves;
-  __shared__ double red_mx[NW][64], red_sm[NW][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nl = COLS ? p.n : p.m;
-  const int line = blk * 64 + lane;
-  const bool valid = line < nl;
-  const int ln = valid ? line : nl - 1;      // clamped (loads only)
-  __shared__ double red_rs[NW][64], red_ra[NW][64];
-  __shared__ float red_lg[NW][64], red_nz[NW][64];
-  __shared__ int red_nf[NW];
-  double mx = 0.0, sm = 0.0, rs = 0.0, ra = 0.0;
-  float lg = 0.0f, nz = 0.0f;                 // sum of log2|x| and count over nonzero x
-  bool nf = false;
-  // the next tile's loads are issued before the current tile is reduced
-  double x[16], y[16] = {};
-  auto load = [&](double* v, int k0) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = k0 + q < p.w ? panel_at<COLS>(p, ln, k0 + q) : 0.0;
-  };
-  int k0 = wave * 16;
-  if (k0 < p.w) load(x, k0);
-  for (; k0 < p.w; k0 += 16 * NW) {
-    if (k0 + 16 * NW < p.w) load(y, k0 + 16 * NW);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      mx = fmax(mx, fabs(x[q]));
-      sm += fabs(x[q]);
-      const bool fin = fabs(x[q]) <= 1.7976931348623157e308;
-      nf |= !fin;
-      const double r = low_bits(x[q]);
-      rs += r;
-      ra += fabs(r);
-      if (fin && x[q] != 0.0) {
-        lg += log2_abs(x[q]);
-        nz += 1.0f;
-      }
-      x[q] = y[q];
-    }
-  }
-  red_mx[wave][lane] = mx;
-  red_sm[wave][lane] = sm;
-  red_rs[wave][lane] = rs;
-  red_ra[wave][lane] = ra;
-  red_lg[wave][lane] = lg;
-  red_nz[wave][lane] = nz;
-  const bool wnf = __any(nf && valid);
-  if (lane == 0) red_nf[wave] = wnf ? 1 : 0;
-  __syncthreads();
-  if (wave != 0) return;
-  if (lane == 0) {
-    int any = 0;
-    for (int w = 0; w < NW; ++w) any |= red_nf[w];
-    if (any) atomicOr(&p.stats[kStatNonFinite], 1u);
-  }
-  if (!valid) return;
-#pragma unroll
-  for (int w = 1; w < NW; ++w) {
-    mx = fmax(mx, red_mx[w][lane]);
-    sm += red_sm[w][lane];
-    rs += red_rs[w][lane];
-    ra += red_ra[w][lane];
-    lg += red_lg[w][lane];
-    nz += red_nz[w][lane];
-  }
-  (COLS ? p.fB : p.eA)[line] = exponent_bound(mx);
-  if (nz > 0.0f && mx <= 1.7976931348623157e308) {
-    const float lam = log2_abs(mx) - lg / nz;
-    atomicMax(&p.stats[COLS ? kStatLamB : kStatLamA], __float_as_uint(fmaxf(lam, 0.0f)));
-  }
-  if (sm > 0.0) {
-    const float kap = (float)log2(mx * (double)p.w / sm);
-    atomicMax(&p.stats[COLS ? kStatKappaB : kStatKappaA], __float_as_uint(fmaxf(kap, 0.0f)));
-  }
-  atomicMax(&p.stats[COLS ? kStatCohB : kStatCohA], __float_as_uint(coherence(rs, ra)));
-}
-
-// A rows: the same 64-row x 16-k tiles as the digit pass (lanes along k,
-// 8 rows x 128 bytes per wave-load); partial max and sum per row, reduced
-// over the 8 lanes of a row and then over the waves.
-__device__ void split_stats_rows(const SplitArgs& p, int blk) {
-  constexpr int NW = kSplitWaves;
-  __shared__ double red_mx[NW][64], red_sm[NW][64], red_rs[NW][64], red_ra[NW][64];
-  __shared__ float red_lg[NW][64], red_nz[NW][64];
-  __shared__ int red_nf[NW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int lr = lane >> 3, kp = 2 * (lane & 7);
-  double mx[8], sm[8], rs[8], ra[8];
-  float lg[8], nz[8];                         // sum of log2|x| and count over nonzero x
-  bool nf = false;
+// The 64 x 16 tile of A rows [64 blk, + 64) (clamped to the last row) and
+// panel columns [k0, k0 + 16) (zero at and past w) into this wave's LDS
+// tile, then row `lane` of it into x.
+__device__ __forceinline__ void load_row_tile(const SplitArgs& p, int blk, int k0, double* tile,
+                                              double (&x)[16]) {
+  const int lane = threadIdx.x & 63;
+  const int lr = lane >> 3, kp = 2 * (lane & 7);   // load role: row lr + 8 i, k pair kp
+  double v[16];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    mx[i] = 0.0;
-    sm[i] = 0.0;
-    rs[i] = 0.0;
-    ra[i] = 0.0;
-    lg[i] = 0.0f;
-    nz[i] = 0.0f;
-  }
-  // the next tile's loads are issued before the current tile is reduced
-  double x[16], y[16] = {};
-  auto load = [&](double* v, int k0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
-      const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
-      v[2 * i] = k0 + kp < p.w ? rp[0] : 0.0;
-      v[2 * i + 1] = k0 + kp + 1 < p.w ? rp[1] : 0.0;
-    }
-  };
-  int k0 = wave * 16;
-  if (k0 < p.w) load(x, k0);
-  for (; k0 < p.w; k0 += 16 * NW) {
-    if (k0 + 16 * NW < p.w) load(y, k0 + 16 * NW);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const double x0 = fabs(x[2 * i]), x1 = fabs(x[2 * i + 1]);
-      mx[i] = fmax(mx[i], fmax(x0, x1));
-      sm[i] += x0 + x1;
-      // rows past m are loaded clamped to the last row: no flag from them
-      const bool live = blk * 64 + lr + 8 * i < p.m;
-      // (each value tested alone: fmax would drop a NaN)
-      nf |= live && !(x0 <= 1.7976931348623157e308 && x1 <= 1.7976931348623157e308);
-      const double r0 = low_bits(x[2 * i]), r1 = low_bits(x[2 * i + 1]);
-      rs[i] += r0 + r1;
-      ra[i] += fabs(r0) + fabs(r1);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const double v = x[2 * i + h];
-        if (v != 0.0 && fabs(v) <= 1.7976931348623157e308) {
-          lg[i] += log2_abs(v);
-          nz[i] += 1.0f;
-        }
-      }
-      x[2 * i] = y[2 * i];
-      x[2 * i + 1] = y[2 * i + 1];
-    }
+    const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
+    const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
+    v[2 * i] = k0 + kp < p.w ? rp[0] : 0.0;
+    v[2 * i + 1] = k0 + kp + 1 < p.w ? rp[1] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    for (int o = 1; o < 8; o <<= 1) {
-      mx[i] = fmax(mx[i], __shfl_xor(mx[i], o));
-      sm[i] += __shfl_xor(sm[i], o);
-      rs[i] += __shfl_xor(rs[i], o);
-      ra[i] += __shfl_xor(ra[i], o);
-      lg[i] += __shfl_xor(lg[i], o);
-      nz[i] += __shfl_xor(nz[i], o);
-    }
-    if ((lane & 7) == 0) {
-      red_mx[wave][lr + 8 * i] = mx[i];
-      red_sm[wave][lr + 8 * i] = sm[i];
-      red_rs[wave][lr + 8 * i] = rs[i];
-      red_ra[wave][lr + 8 * i] = ra[i];
-      red_lg[wave][lr + 8 * i] = lg[i];
-      red_nz[wave][lr + 8 * i] = nz[i];
-    }
+    double* t = tile + (lr + 8 * i) * kTileStride + kp;
+    t[0] = v[2 * i];
+    t[1] = v[2 * i + 1];
   }
-  const bool wnf = __any(nf);
-  if (lane == 0) red_nf[wave] = wnf ? 1 : 0;
-  __syncthreads();
-  if (wave != 0) return;
-  if (lane == 0) {
-    int any = 0;
-    for (int w = 0; w < NW; ++w) any |= red_nf[w];
-    if (any) atomicOr(&p.stats[kStatNonFinite], 1u);
-  }
-  const int row = blk * 64 + lane;
-  if (row >= p.m) return;
-  double m2 = red_mx[0][lane], s2 = red_sm[0][lane], r2 = red_rs[0][lane], a2 = red_ra[0][lane];
-  float g2 = red_lg[0][lane], z2 = red_nz[0][lane];
+  // the same wave reads the tile back: its LDS accesses complete in order
 #pragma unroll
-  for (int w = 1; w < NW; ++w) {
-    m2 = fmax(m2, red_mx[w][lane]);
-    s2 += red_sm[w][lane];
-    r2 += red_rs[w][lane];
-    a2 += red_ra[w][lane];
-    g2 += red_lg[w][lane];
-    z2 += red_nz[w][lane];
-  }
-  p.eA[row] = exponent_bound(m2);
-  if (z2 > 0.0f && m2 <= 1.7976931348623157e308) {
-    const float lam = log2_abs(m2) - g2 / z2;
-    atomicMax(&p.stats[kStatLamA], __float_as_uint(fmaxf(lam, 0.0f)));
-  }
-  if (s2 > 0.0) {
-    const float kap = (float)log2(m2 * (double)p.w / s2);
-    atomicMax(&p.stats[kStatKappaA], __float_as_uint(fmaxf(kap, 0.0f)));
-  }
-  atomicMax(&p.stats[kStatCohA], __float_as_uint(coherence(r2, a2)));
+  for (int q = 0; q < 16; ++q) x[q] = tile[lane * kTileStride + q];
+}
+
+// Panel columns [k0, k0 + 16) of B column `col` (zero at and past w).
+__device__ __forceinline__ void load_col_tile(const SplitArgs& p, int col, int k0, double (&x)[16]) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    x[q] = k0 + q < p.w ? p.B[(int64_t)(p.k0 + k0 + q) * p.ldb + col] : 0.0;
 }
 
 __global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs p) {
+  __shared__ double tiles[kSplitWaves][64 * kTileStride];
+  __shared__ double red[kSplitWaves][kPartFields][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ga = (p.m + 63) / 64;
-  if ((int)blockIdx.x < ga) split_stats_rows(p, blockIdx.x);
-  else split_stats_lines<true>(p, blockIdx.x - ga);
+  const bool rows = (int)blockIdx.x < ga;
+  const int blk = rows ? blockIdx.x : blockIdx.x - ga;
+  const int nl = rows ? p.m : p.n;
+  const int line = blk * 64 + lane;
+  const bool valid = line < nl;
+  const int k0 = blockIdx.y * kSlabK + 16 * wave;
+  double x[16];
+  if (rows) load_row_tile(p, blk, k0, tiles[wave], x);
+  else load_col_tile(p, valid ? line : nl - 1, k0, x);
+  double mx = 0.0, sm = 0.0, rs = 0.0, ra = 0.0;
+  float lg = 0.0f, nz = 0.0f;                 // sum of log2|x| and count over finite nonzero x
+  bool nf = false;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double a = fabs(x[q]);
+    mx = fmax(mx, a);
+    sm += a;
+    const bool fin = a <= 1.7976931348623157e308;   // (tested alone: fmax drops a NaN)
+    nf |= !fin;
+    const double r = low_bits(x[q]);
+    rs += r;
+    ra += fabs(r);
+    if (fin && a != 0.0) {
+      lg += log2_abs(x[q]);
+      nz += 1.0f;
+    }
+  }
+  if (__any(nf && valid) && lane == 0) atomicOr(&p.stats[kStatNonFinite], 1u);
+  red[wave][0][lane] = mx;
+  red[wave][1][lane] = sm;
+  red[wave][2][lane] = rs;
+  red[wave][3][lane] = ra;
+  red[wave][4][lane] = (double)lg;
+  red[wave][5][lane] = (double)nz;
+  __syncthreads();
+  if (wave != 0 || !valid) return;
+#pragma unroll
+  for (int w = 1; w < kSplitWaves; ++w) {
+    mx = fmax(mx, red[w][0][lane]);
+    sm += red[w][1][lane];
+    rs += red[w][2][lane];
+    ra += red[w][3][lane];
+  }
+  double lgd = red[0][4][lane], nzd = red[0][5][lane];
+#pragma unroll
+  for (int w = 1; w < kSplitWaves; ++w) {
+    lgd += red[w][4][lane];
+    nzd += red[w][5][lane];
+  }
+  const int64_t L = (int64_t)p.m + p.n;
+  const int64_t fs = (int64_t)p.nslab * L;            // doubles per field
+  double* q = p.part + (int64_t)blockIdx.y * L + (rows ? line : p.m + line);
+  q[0] = mx;
+  q[fs] = sm;
+  q[2 * fs] = rs;
+  q[3 * fs] = ra;
+  q[4 * fs] = lgd;
+  q[5 * fs] = nzd;
 }
 
-template <int FMT, bool COLS>
-__device__ void split_digit_lines(const SplitArgs& p, int blk, int s) {
-  constexpr int H = digit_h(FMT), T = digit_t(FMT), ESZ = digit_bytes(FMT);
-  constexpr int NW = kSplitWaves;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nl = COLS ? p.n : p.m;
-  const int line = blk * 64 + lane;
-  if (line >= nl) return;                    // no barrier follows
-  const int e = (COLS ? p.fB : p.eA)[line];
-  uint8_t* dig = (uint8_t*)(COLS ? p.digB : p.digA);
-  const int64_t plane = COLS ? p.planeB : p.planeA;   // elements per plane
-  const int64_t blkel = (int64_t)nl * 16;              // elements per k16 block
-  // the next tile's loads are issued before the current tile's digits
-  double x[16];
-  auto load = [&](double* v, int k0) {
+// Largest of v over the wave (v >= 0).
+__device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = k0 + q < p.w ? panel_at<COLS>(p, line, k0 + q) : 0.0;
-  };
-  int kf = wave * 16;
-  if (kf < p.Wp) load(x, kf);
-  for (int k0 = kf; k0 < p.Wp; k0 += 16 * NW) {
-    double r[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) r[q] = ldexp(x[q], -e);
-    if (k0 + 16 * NW < p.Wp) load(x, k0 + 16 * NW);
-    const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
-    if (FMT == 2) {
-      uint32_t w[kSplitMaxSlices][4];
-      int8_digits(r, s, w);
-#pragma unroll
-      for (int l = 0; l < kSplitMaxSlices; ++l)
-        if (l < s) *(uint4*)(dig + l * plane + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
-      continue;
+  for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void split_combine_kernel(SplitArgs p) {
+  const int64_t L = (int64_t)p.m + p.n;
+  const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = line < L;
+  const bool col = line >= p.m;
+  float kap = 0.0f, coh = 0.0f, lam = 0.0f;
+  if (valid) {
+    const int64_t fs = (int64_t)p.nslab * L;
+    const double* q = p.part + line;
+    double mx = 0.0, sm = 0.0, rs = 0.0, ra = 0.0, lg = 0.0, nz = 0.0;
+    for (int sl = 0; sl < p.nslab; ++sl, q += L) {
+      mx = fmax(mx, q[0]);
+      sm += q[fs];
+      rs += q[2 * fs];
+      ra += q[3 * fs];
+      lg += q[4 * fs];
+      nz += q[5 * fs];
     }
-    int shift = H;
-    for (int l = 0; l < s; ++l) {
-      uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const double y = ldexp(r[q], shift);
-        const double d = rint(y);
-        r[q] = y - d;
-        if (FMT == 0)
-          w32[q >> 1] |= (__float_as_uint((float)ldexp(d, -T * l)) >> 16) << (16 * (q & 1));
-        else
-          w32[q >> 2] |= (uint32_t)e4m3_of_int((int)d) << (8 * (q & 3));
-      }
-      shift = T;
-      uint8_t* dst = dig + (l * plane + pos) * ESZ;
-      ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
-      if (FMT == 0) ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
-    }
+    (col ? p.fB : p.eA)[col ? line - p.m : line] = exponent_bound(mx);
+    if (nz > 0.0 && mx <= 1.7976931348623157e308)
+      lam = fmaxf(log2_abs(mx) - (float)(lg / nz), 0.0f);
+    if (sm > 0.0) kap = fmaxf((float)log2(mx * (double)p.w / sm), 0.0f);
+    coh = coherence(rs, ra);
+  }
+  // a wave may hold A rows and B columns: one maximum per operand
+  const float ka = wave_max(valid && !col ? kap : 0.0f), kb = wave_max(valid && col ? kap : 0.0f);
+  const float ca = wave_max(valid && !col ? coh : 0.0f), cb = wave_max(valid && col ? coh : 0.0f);
+  const float la = wave_max(valid && !col ? lam : 0.0f), lb = wave_max(valid && col ? lam : 0.0f);
+  if ((threadIdx.x & 63) == 0) {
+    if (ka > 0.0f) atomicMax(&p.stats[kStatKappaA], __float_as_uint(ka));
+    if (kb > 0.0f) atomicMax(&p.stats[kStatKappaB], __float_as_uint(kb));
+    if (ca > 0.0f) atomicMax(&p.stats[kStatCohA], __float_as_uint(ca));
+    if (cb > 0.0f) atomicMax(&p.stats[kStatCohB], __float_as_uint(cb));
+    if (la > 0.0f) atomicMax(&p.stats[kStatLamA], __float_as_uint(la));
+    if (lb > 0.0f) atomicMax(&p.stats[kStatLamB], __float_as_uint(lb));
   }
 }
 
-// A rows: each wave stages a 64-row x 16-k tile through its own LDS region
-// (read with lanes along k, 8 rows x 128 bytes per wave-load; row stride 18
-// doubles, so the per-row 16-byte reads of 16 lanes hit distinct banks),
-// then lane = row as in split_digit_lines.
-constexpr int kTileStride = 18;              // doubles per staged row
-
+// The digits of one 16-k tile of one line (x scaled by 2^-e), stored at
+// element `pos` of each of the first s planes.
 template <int FMT>
-__device__ void split_digit_rows(const SplitArgs& p, int blk, int s, double* tile) {
+__device__ __forceinline__ void put_digits(uint8_t* dig, int64_t plane, int64_t pos, int s,
+                                           const double (&x)[16], int e) {
   constexpr int H = digit_h(FMT), T = digit_t(FMT), ESZ = digit_bytes(FMT);
-  constexpr int NW = kSplitWaves;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int line = blk * 64 + lane;
-  const bool valid = line < p.m;
-  const int e = p.eA[valid ? line : p.m - 1];
-  uint8_t* dig = (uint8_t*)p.digA;
-  const int64_t blkel = (int64_t)p.m * 16;
-  const int lr = lane >> 3, kp = 2 * (lane & 7);   // load role: row lr + 8 i, k pair kp
-  // the next tile's loads are issued before the current tile's digits
-  double x[16];
-  auto load = [&](int k0) {
+  double r[16];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int row = min(blk * 64 + lr + 8 * i, p.m - 1);
-      const double* rp = p.A + (int64_t)row * p.lda + p.k0 + k0 + kp;
-      x[2 * i] = k0 + kp < p.w ? rp[0] : 0.0;
-      x[2 * i + 1] = k0 + kp + 1 < p.w ? rp[1] : 0.0;
+  for (int q = 0; q < 16; ++q) r[q] = ldexp(x[q], -e);
+  if (FMT == 2) {
+    uint32_t w[kSplitMaxSlices][4];
+    int8_digits(r, s, w);
+#pragma unroll
+    for (int l = 0; l < kSplitMaxSlices; ++l)
+      if (l < s) *(uint4*)(dig + l * plane + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
+    return;
+  }
+  int shift = H;
+  for (int l = 0; l < s; ++l) {
+    uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double y = ldexp(r[q], shift);
+      const double d = rint(y);
+      r[q] = y - d;
+      if (FMT == 0)
+        w32[q >> 1] |= (__float_as_uint((float)ldexp(d, -T * l)) >> 16) << (16 * (q & 1));
+      else
+        w32[q >> 2] |= (uint32_t)e4m3_of_int((int)d) << (8 * (q & 3));
     }
-  };
-  int kf = wave * 16;
-  if (kf < p.Wp) load(kf);
-  for (int k0 = kf; k0 < p.Wp; k0 += 16 * NW) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      double* t = tile + (lr + 8 * i) * kTileStride + kp;
-      t[0] = x[2 * i];
-      t[1] = x[2 * i + 1];
-    }
-    double r[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) r[q] = ldexp(tile[lane * kTileStride + q], -e);
-    if (k0 + 16 * NW < p.Wp) load(k0 + 16 * NW);
-    if (valid && FMT == 2) {
-      const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
-      uint32_t w[kSplitMaxSlices][4];
-      int8_digits(r, s, w);
-#pragma unroll
-      for (int l = 0; l < kSplitMaxSlices; ++l)
-        if (l < s)
-          *(uint4*)(dig + l * p.planeA + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
-    } else if (valid) {
-      const int64_t pos = (int64_t)(k0 >> 4) * blkel + (int64_t)line * 16;
-      int shift = H;
-      for (int l = 0; l < s; ++l) {
-        uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const double y = ldexp(r[q], shift);
-          const double d = rint(y);
-          r[q] = y - d;
-          if (FMT == 0)
-            w32[q >> 1] |= (__float_as_uint((float)ldexp(d, -T * l)) >> 16) << (16 * (q & 1));
-          else
-            w32[q >> 2] |= (uint32_t)e4m3_of_int((int)d) << (8 * (q & 3));
-        }
-        shift = T;
-        uint8_t* dst = dig + (l * p.planeA + pos) * ESZ;
-        ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
-        if (FMT == 0) ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
-      }
-    }
+    shift = T;
+    uint8_t* dst = dig + (l * plane + pos) * ESZ;
+    ((uint4*)dst)[0] = make_uint4(w32[0], w32[1], w32[2], w32[3]);
+    if (FMT == 0) ((uint4*)dst)[1] = make_uint4(w32[4], w32[5], w32[6], w32[7]);
   }
 }
 
@@ -548,11 +406,24 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArg
   __shared__ double tiles[kSplitWaves][64 * kTileStride];
   const int s = panel_slices(p.stats, p.fixed_s, p.smin, p.smax, p.tau_bits, p.log2k, p.log2w,
                              digit_h(FMT), digit_t(FMT));
-  if (blockIdx.x == 0 && threadIdx.x == 0) *p.slices_out = s;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.slices_out = s;
   if (s == 0) return;                         // the FP64 kernel computes this panel
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k0 = blockIdx.y * kSlabK + 16 * wave;
+  if (k0 >= p.Wp) return;                     // (FP8: a half slab at the end; no barrier follows)
   const int ga = (p.m + 63) / 64;
-  if ((int)blockIdx.x < ga) split_digit_rows<FMT>(p, blockIdx.x, s, tiles[threadIdx.x >> 6]);
-  else split_digit_lines<FMT, true>(p, blockIdx.x - ga, s);
+  const bool rows = (int)blockIdx.x < ga;
+  const int blk = rows ? blockIdx.x : blockIdx.x - ga;
+  const int nl = rows ? p.m : p.n;
+  const int line = blk * 64 + lane;
+  double x[16];
+  if (rows) load_row_tile(p, blk, k0, tiles[wave], x);
+  else if (line < nl) load_col_tile(p, line, k0, x);
+  if (line >= nl) return;
+  const int e = (rows ? p.eA : p.fB)[line];
+  // k16-block-major planes: (plane, line, kk) at plane * stride + (kk / 16) lines 16 + line 16 + kk % 16
+  const int64_t pos = (int64_t)(k0 >> 4) * ((int64_t)nl * 16) + (int64_t)line * 16;
+  put_digits<FMT>((uint8_t*)(rows ? p.digA : p.digB), rows ? p.planeA : p.planeB, pos, s, x, e);
 }
 
 // clears the per-panel statistics before the split of a panel
@@ -1502,14 +1373,16 @@ hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float
 
 // ---- launchers ----------------------------------------------------------------
 hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
-  const int g = (a.m + 63) / 64 + (a.n + 63) / 64;
-  hipLaunchKernelGGL(split_stats_kernel, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+  const dim3 grid((a.m + 63) / 64 + (a.n + 63) / 64, a.nslab);
+  const int gc = (int)(((int64_t)a.m + a.n + 255) / 256);
+  hipLaunchKernelGGL(split_stats_kernel, grid, dim3(64 * kSplitWaves), 0, s, a);
+  hipLaunchKernelGGL(split_combine_kernel, dim3(gc), dim3(256), 0, s, a);
   if (a.fmt == 0)
-    hipLaunchKernelGGL(split_digits_kernel<0>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+    hipLaunchKernelGGL(split_digits_kernel<0>, grid, dim3(64 * kSplitWaves), 0, s, a);
   else if (a.fmt == 1)
-    hipLaunchKernelGGL(split_digits_kernel<1>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+    hipLaunchKernelGGL(split_digits_kernel<1>, grid, dim3(64 * kSplitWaves), 0, s, a);
   else
-    hipLaunchKernelGGL(split_digits_kernel<2>, dim3(g), dim3(64 * kSplitWaves), 0, s, a);
+    hipLaunchKernelGGL(split_digits_kernel<2>, grid, dim3(64 * kSplitWaves), 0, s, a);
   return hipGetLastError();
 }
 

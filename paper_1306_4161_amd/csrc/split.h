@@ -30,6 +30,8 @@ struct SplitArgs {
   void* digB; int64_t planeB;        // planes of n x Wp digits (B transposed)
   int32_t* eA; int32_t* fB;          // per-row / per-column exponents
   uint32_t* stats;                   // kStatWords words, cleared before the statistics pass
+  double* part;                      // per-slab partial sums of every line (split_part_doubles)
+  int32_t nslab;                     // 64-k slabs of the padded panel: ceil(Wp / 64)
   int32_t* slices_out;               // the panel's slice count (0: the FP64 kernel computes it)
   int32_t fixed_s, smin, tau_bits;   // slice-count choice: fixed count, bounds, target bits
   float log2k;                       // log2 of the product's inner dimension k
@@ -50,8 +52,15 @@ struct SliceArgs {
   double* dump;                      // 64 doubles of workspace: INT8 stores of lanes outside an item
 };
 
-// Statistics pass (exponents, kappa) over both operands, then the digit
-// pass, which writes only the panel's chosen number of planes.
+// Doubles of the per-slab partial statistics of a panel of padded width Wp
+// over m + n lines.
+constexpr int64_t split_part_doubles(int64_t m, int64_t n, int64_t Wp) {
+  return 6 * ((Wp + 63) / 64) * (m + n);
+}
+
+// Statistics pass (per-slab partial sums), their combination (exponents,
+// kappa and the other panel statistics), then the digit pass, which writes
+// only the panel's chosen number of planes.
 hipError_t launch_split(const SplitArgs& a, hipStream_t s);
 hipError_t launch_slices(int fmt, const SliceArgs& a, int grid, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);

@@ -256,14 +256,17 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch_array():
 
 def test_split_lookahead_doubles_the_panel_sets():
     # look-ahead in a split form: a second set of digit planes (max_slices
-    # planes of m x Wp and n x Wp digits) and exponents; nothing for FP64
+    # planes of m x Wp and n x Wp digits), exponents and partial statistics;
+    # nothing for FP64
     al = lambda x: (x + 255) // 256 * 256
     for prec, esz, planes in ((hs.SPLIT_BF16, 2, 7), (hs.SPLIT_INT8, 1, 8)):
         m, n, k, M = 600, 520, 1000, 128
         plain = hs.Plan(n, 2, 2, 4, 32, M, m=m, k=k, prec=prec)
         ahead = hs.Plan(n, 2, 2, 4, 32, M, m=m, k=k, prec=prec, lookahead=1)
         Wp = 128
-        extra = (al(planes * m * Wp * esz) + al(planes * n * Wp * esz) + al(4 * m) + al(4 * n))
+        part = 6 * (Wp // 64) * (m + n) * 8       # per-slab partial statistics
+        extra = (al(planes * m * Wp * esz) + al(planes * n * Wp * esz) + al(4 * m) + al(4 * n)
+                 + al(part))
         assert ahead.workspace_size == plain.workspace_size + extra
         assert ahead.work_items().tolist() == plain.work_items().tolist()
         plain.close(); ahead.close()
