@@ -44,17 +44,28 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef int i16v __attribute__((ext_vector_type(16)));
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // digit format FMT (0: BF16, 1: FP8-e4m3, 2: INT8): first shift H, later
 // shift T, bytes per stored digit
 constexpr int digit_h(int fmt) { return fmt == 0 ? 8 : fmt == 1 ? 4 : 6; }
 constexpr int digit_t(int fmt) { return fmt == 0 ? 9 : fmt == 1 ? 5 : 8; }
 constexpr int digit_bytes(int fmt) { return fmt == 0 ? 2 : 1; }
 
-// INT8 digits of the 16 values r[] (already scaled by 2^-e): s digits per
+// INT8 digits of the 16 values r[] (already scaled by 2^-e): S digits per
 // value (round half to even), then the carry pass into the int8 range;
-// plane l's 16 bytes are packed into w[l][0..3].
-__device__ __forceinline__ void int8_digits(const double* r, int s,
-                                            uint32_t (&w)[kSplitMaxSlices][4]) {
+// plane l's 16 bytes are packed into w[l][0..3].  S is a template parameter
+// so that the unrolled loops carry no branches.
+template <int S>
+__device__ __forceinline__ void int8_digits(const double* r, uint32_t (&w)[kSplitMaxSlices][4]) {
+  constexpr int s = S;
 #pragma unroll
   for (int l = 0; l < kSplitMaxSlices; ++l)
 #pragma unroll
@@ -255,8 +266,11 @@ __device__ __forceinline__ void load_col_tile(const SplitArgs& p, int col, int k
 }
 
 __global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs p) {
+  // the staging tiles, then (once every wave has read its tile) the waves'
+  // partial sums [wave][field][lane]: 37 KB, four blocks per CU
   __shared__ double tiles[kSplitWaves][64 * kTileStride];
-  __shared__ double red[kSplitWaves][kPartFields][64];
+  static_assert(kSplitWaves * kPartFields * 64 <= kSplitWaves * 64 * kTileStride, "reuse");
+  double* red = &tiles[0][0];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ga = (p.m + 63) / 64;
   const bool rows = (int)blockIdx.x < ga;
@@ -287,26 +301,28 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_stats_kernel(SplitArgs
     }
   }
   if (__any(nf && valid) && lane == 0) atomicOr(&p.stats[kStatNonFinite], 1u);
-  red[wave][0][lane] = mx;
-  red[wave][1][lane] = sm;
-  red[wave][2][lane] = rs;
-  red[wave][3][lane] = ra;
-  red[wave][4][lane] = (double)lg;
-  red[wave][5][lane] = (double)nz;
+  __syncthreads();                            // every tile has been read
+  auto at = [&](int w, int f) -> double& { return red[(w * kPartFields + f) * 64 + lane]; };
+  at(wave, 0) = mx;
+  at(wave, 1) = sm;
+  at(wave, 2) = rs;
+  at(wave, 3) = ra;
+  at(wave, 4) = (double)lg;
+  at(wave, 5) = (double)nz;
   __syncthreads();
   if (wave != 0 || !valid) return;
 #pragma unroll
   for (int w = 1; w < kSplitWaves; ++w) {
-    mx = fmax(mx, red[w][0][lane]);
-    sm += red[w][1][lane];
-    rs += red[w][2][lane];
-    ra += red[w][3][lane];
+    mx = fmax(mx, at(w, 0));
+    sm += at(w, 1);
+    rs += at(w, 2);
+    ra += at(w, 3);
   }
-  double lgd = red[0][4][lane], nzd = red[0][5][lane];
+  double lgd = at(0, 4), nzd = at(0, 5);
 #pragma unroll
   for (int w = 1; w < kSplitWaves; ++w) {
-    lgd += red[w][4][lane];
-    nzd += red[w][5][lane];
+    lgd += at(w, 4);
+    nzd += at(w, 5);
   }
   const int64_t L = (int64_t)p.m + p.n;
   const int64_t fs = (int64_t)p.nslab * L;            // doubles per field
@@ -326,9 +342,21 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void split_combine_kernel(SplitArgs p) {
+constexpr int kCombineThreads = 256;
+
+// stats[w] = max(stats[w], v) for v >= 0 (float bits), skipped when the word
+// already holds v or more: the panel's maxima settle after a few updates, so
+// most blocks then issue no atomic at all (the words are read through to L2)
+__device__ __forceinline__ void stat_max(uint32_t* word, float v) {
+  if (!(v > 0.0f)) return;
+  const uint32_t bits = __float_as_uint(v);
+  if (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= bits) return;
+  atomicMax(word, bits);
+}
+
+__global__ __launch_bounds__(kCombineThreads) void split_combine_kernel(SplitArgs p) {
   const int64_t L = (int64_t)p.m + p.n;
-  const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t line = (int64_t)blockIdx.x * kCombineThreads + threadIdx.x;
   const bool valid = line < L;
   const bool col = line >= p.m;
   float kap = 0.0f, coh = 0.0f, lam = 0.0f;
@@ -336,6 +364,8 @@ __global__ __launch_bounds__(256) void split_combine_kernel(SplitArgs p) {
     const int64_t fs = (int64_t)p.nslab * L;
     const double* q = p.part + line;
     double mx = 0.0, sm = 0.0, rs = 0.0, ra = 0.0, lg = 0.0, nz = 0.0;
+    // (unrolled: the loads of several slabs in flight; the sums stay in slab order)
+#pragma unroll 4
     for (int sl = 0; sl < p.nslab; ++sl, q += L) {
       mx = fmax(mx, q[0]);
       sm += q[fs];
@@ -350,39 +380,51 @@ __global__ __launch_bounds__(256) void split_combine_kernel(SplitArgs p) {
     if (sm > 0.0) kap = fmaxf((float)log2(mx * (double)p.w / sm), 0.0f);
     coh = coherence(rs, ra);
   }
-  // a wave may hold A rows and B columns: one maximum per operand
-  const float ka = wave_max(valid && !col ? kap : 0.0f), kb = wave_max(valid && col ? kap : 0.0f);
-  const float ca = wave_max(valid && !col ? coh : 0.0f), cb = wave_max(valid && col ? coh : 0.0f);
-  const float la = wave_max(valid && !col ? lam : 0.0f), lb = wave_max(valid && col ? lam : 0.0f);
-  if ((threadIdx.x & 63) == 0) {
-    if (ka > 0.0f) atomicMax(&p.stats[kStatKappaA], __float_as_uint(ka));
-    if (kb > 0.0f) atomicMax(&p.stats[kStatKappaB], __float_as_uint(kb));
-    if (ca > 0.0f) atomicMax(&p.stats[kStatCohA], __float_as_uint(ca));
-    if (cb > 0.0f) atomicMax(&p.stats[kStatCohB], __float_as_uint(cb));
-    if (la > 0.0f) atomicMax(&p.stats[kStatLamA], __float_as_uint(la));
-    if (lb > 0.0f) atomicMax(&p.stats[kStatLamB], __float_as_uint(lb));
+  // the block's maxima, one per statistic and operand (a block may hold A
+  // rows and B columns), then one thread folds them into the panel's
+  __shared__ float bmax[kCombineThreads / 64][6];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float v[6] = {valid && !col ? kap : 0.0f, valid && col ? kap : 0.0f,
+                      valid && !col ? coh : 0.0f, valid && col ? coh : 0.0f,
+                      valid && !col ? lam : 0.0f, valid && col ? lam : 0.0f};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float w = wave_max(v[i]);
+    if (lane == 0) bmax[wave][i] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    constexpr int kWord[6] = {kStatKappaA, kStatKappaB, kStatCohA, kStatCohB, kStatLamA,
+                              kStatLamB};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      float m = bmax[0][i];
+      for (int w = 1; w < kCombineThreads / 64; ++w) m = fmaxf(m, bmax[w][i]);
+      stat_max(&p.stats[kWord[i]], m);
+    }
   }
 }
 
 // The digits of one 16-k tile of one line (x scaled by 2^-e), stored at
-// element `pos` of each of the first s planes.
-template <int FMT>
-__device__ __forceinline__ void put_digits(uint8_t* dig, int64_t plane, int64_t pos, int s,
+// element `pos` of each of the first S planes.
+template <int FMT, int S>
+__device__ __forceinline__ void put_digits(uint8_t* dig, int64_t plane, int64_t pos,
                                            const double (&x)[16], int e) {
   constexpr int H = digit_h(FMT), T = digit_t(FMT), ESZ = digit_bytes(FMT);
   double r[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) r[q] = ldexp(x[q], -e);
-  if (FMT == 2) {
+  if constexpr (FMT == 2) {
     uint32_t w[kSplitMaxSlices][4];
-    int8_digits(r, s, w);
+    int8_digits<S>(r, w);
 #pragma unroll
-    for (int l = 0; l < kSplitMaxSlices; ++l)
-      if (l < s) *(uint4*)(dig + l * plane + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
+    for (int l = 0; l < S; ++l)
+      *(uint4*)(dig + l * plane + pos) = make_uint4(w[l][0], w[l][1], w[l][2], w[l][3]);
     return;
   }
   int shift = H;
-  for (int l = 0; l < s; ++l) {
+#pragma unroll
+  for (int l = 0; l < S; ++l) {
     uint32_t w32[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -423,7 +465,11 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArg
   const int e = (rows ? p.eA : p.fB)[line];
   // k16-block-major planes: (plane, line, kk) at plane * stride + (kk / 16) lines 16 + line 16 + kk % 16
   const int64_t pos = (int64_t)(k0 >> 4) * ((int64_t)nl * 16) + (int64_t)line * 16;
-  put_digits<FMT>((uint8_t*)(rows ? p.digA : p.digB), rows ? p.planeA : p.planeB, pos, s, x, e);
+  uint8_t* dig = (uint8_t*)(rows ? p.digA : p.digB);
+  const int64_t plane = rows ? p.planeA : p.planeB;
+  static_for<1, kSplitMaxSlices + 1>([&](auto S) {
+    if (s == S.value) put_digits<FMT, S.value>(dig, plane, pos, x, e);
+  });
 }
 
 // clears the per-panel statistics before the split of a panel
@@ -473,15 +519,6 @@ constexpr int kBf16Lds = 152 * 1024;  // LDS ring budget (bytes)
 constexpr int bf16_stages(int S) {
   return (kBf16Lds / (S * (kBf16TM + kBf16TN) * 32)) < 5 ? (kBf16Lds / (S * (kBf16TM + kBf16TN) * 32))
                                                           : 5;
-}
-
-// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
 }
 
 // One C write of a split epilogue as exactly one vector-memory instruction,
@@ -1374,9 +1411,9 @@ hipError_t launch_mfma_probe(int fmt, const void* a, const void* b, int k, float
 // ---- launchers ----------------------------------------------------------------
 hipError_t launch_split(const SplitArgs& a, hipStream_t s) {
   const dim3 grid((a.m + 63) / 64 + (a.n + 63) / 64, a.nslab);
-  const int gc = (int)(((int64_t)a.m + a.n + 255) / 256);
+  const int gc = (int)(((int64_t)a.m + a.n + kCombineThreads - 1) / kCombineThreads);
   hipLaunchKernelGGL(split_stats_kernel, grid, dim3(64 * kSplitWaves), 0, s, a);
-  hipLaunchKernelGGL(split_combine_kernel, dim3(gc), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(split_combine_kernel, dim3(gc), dim3(kCombineThreads), 0, s, a);
   if (a.fmt == 0)
     hipLaunchKernelGGL(split_digits_kernel<0>, grid, dim3(64 * kSplitWaves), 0, s, a);
   else if (a.fmt == 1)
