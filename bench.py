@@ -42,7 +42,6 @@ FP64 triple loop) on a bounded slice of the same product.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -85,11 +84,10 @@ def parse():
 
 
 def source_hash(*names):
-    h = hashlib.sha256()
-    for nm in names:
-        with open(os.path.join(ROOT, "paper_1306_4161_amd", "csrc", nm), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the code (not the comments) of the named csrc files, as the
+    profile summaries record it."""
+    from paper_1306_4161_amd.profiling import source_hash as code_hash
+    return code_hash(*names)
 
 
 def committed_traffic(kernel: str, workload: str, src_hash: str):

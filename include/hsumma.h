@@ -31,14 +31,19 @@
  * processor, see hsumma_work_items) into `ws` with a small kernel, then
  * launches the update kernels, which read their operands and the workspace
  * only.  A plan is a host object; a HIP graph it captures (opts.use_graph)
- * is owned by the plan and released by hsumma_plan_destroy().  A, B, C and
+ * and the second stream and events of a split-form plan with look-ahead
+ * (opts.lookahead) are owned by the plan and released by
+ * hsumma_plan_destroy().  A, B, C and
  * `ws` must be ordinary (coarse-grained) device memory of the current
  * device: the split forms add into C with FP64 atomic adds, which need it.
  *
  * Streams and synchronisation.  `stream` is a hipStream_t passed as void*
  * (NULL = the null stream).  All compute calls are asynchronous on it and
  * never synchronise the device or the host; only hsumma_panel_slices waits
- * for `stream`.  A, B, C and ws must not overlap.  Calls that share a
+ * for `stream`.  hsumma_run of a look-ahead plan also launches on the
+ * plan's own stream, ordered by events after the work already queued on
+ * `stream`, and makes `stream` wait for all of it before the call's last
+ * launch, so the call still ends on `stream`.  A, B, C and ws must not overlap.  Calls that share a
  * workspace must be ordered (one stream, or events).
  *
  * Non-finite inputs.  The FP64 path follows IEEE arithmetic (an Inf or NaN
@@ -280,8 +285,10 @@ int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, voi
  * FP8-e4m3 or INT8 digit, stored k16-block-major: digit (plane, row, k) at
  * plane*m*Wp + (k/16)*m*16 + row*16 + k%16), the B digit planes (the same
  * with n columns: B transposed), the int32 row exponents of A and column
- * exponents of B.  They hold the most recently split panel; of its planes
- * only the first s (its slice count, see hsumma_panel_slices) are written.
+ * exponents of B.  They hold the most recently split panel (with look-ahead:
+ * the most recently split even outer panel; odd ones use a second set); of
+ * its planes only the first s (its slice count, see hsumma_panel_slices)
+ * are written.
  * Lets a caller inspect the split; HSUMMA_ERR_UNSUPPORTED for the FP64
  * path.
  */

@@ -89,8 +89,9 @@ struct hsumma_plan_s {
   int32_t Wp = 0;              // padded panel width
   size_t off_digA = 0, off_digB = 0, off_eA = 0, off_fB = 0, off_part = 0, off_stats = 0,
          off_slices = 0, off_dump = 0, ws_bytes = 0;
-  // split forms with look-ahead: a second set of digit planes and exponents
-  // (panel g uses set g % 2), the second stream and its events
+  // split forms with look-ahead: a second set of digit planes, exponents and
+  // partial statistics (panel g uses set g % 2), the second stream and its
+  // events
   bool lookahead = false;
   size_t off_digA1 = 0, off_digB1 = 0, off_eA1 = 0, off_fB1 = 0, off_part1 = 0;
   hipStream_t aux = nullptr;

@@ -35,11 +35,40 @@ COPY_BYTES = 1 << 30
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+def code_only(text: str) -> str:
+    """C++ source with its comments removed and white space collapsed (string
+    and character literals kept as written)."""
+    out = []
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(*names) -> str:
+    """Hash of the code of the named csrc files: a profile summary records it,
+    and bench.py uses a summary's counters only while the code is unchanged
+    (edits to comments or layout do not count)."""
     h = hashlib.sha256()
     for nm in names:
-        with open(os.path.join(ROOT, "paper_1306_4161_amd", "csrc", nm), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1306_4161_amd", "csrc", nm), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode("utf-8"))
     return h.hexdigest()[:16]
 
 
