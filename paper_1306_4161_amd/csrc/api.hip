@@ -743,6 +743,11 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     // BF16 steps in groups of 64 k, INT8 in pairs of 32-k steps
     const int64_t pad = p->fmt == 1 ? hs::kSplitChunk : 64;
     const int64_t Wp = (M + pad - 1) / pad * pad;
+    if ((Wp + 63) / 64 > 65535) {
+      delete p;
+      return invalid("split forms need an outer block M of at most 4194240 (the split kernels "
+                     "take one grid row per 64 columns of the panel, at most 65535)");
+    }
     p->Wp = (int32_t)Wp;
     const int64_t esz = p->fmt == 0 ? 2 : 1;
     // the slice kernels address each operand's digit planes through a buffer

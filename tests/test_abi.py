@@ -254,6 +254,13 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch_array():
     big.close()
 
 
+def test_split_outer_block_fits_the_split_grid():
+    # one grid row of the split kernels per 64 panel columns, at most 65535
+    hs.Plan(64, 1, 1, 1, 64, 65535 * 64, k=65535 * 64, prec=hs.SPLIT_BF16).close()
+    with pytest.raises(hs.HsummaError):
+        hs.Plan(64, 1, 1, 1, 64, 65535 * 64 + 64, k=65535 * 64 + 64, prec=hs.SPLIT_BF16)
+
+
 def test_split_lookahead_doubles_the_panel_sets():
     # look-ahead in a split form: a second set of digit planes (max_slices
     # planes of m x Wp and n x Wp digits), exponents and partial statistics;
