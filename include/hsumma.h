@@ -116,13 +116,17 @@ typedef struct {
                       /* 0 = direct-to-LDS loads where alignment allows         */
   int32_t waves;      /* FP64 path: waves per workgroup of the macro-tile's     */
                       /* kernel; 0 => the tile's first compiled configuration   */
-  int32_t lookahead;  /* hsumma_lu: 1 = factor the next panel while the rest of */
-                      /* the trailing update runs on a second stream.  Split    */
-                      /* forms: 1 = hsumma_run splits outer panel g + 1 on a    */
-                      /* second stream while the products of panel g run (the   */
-                      /* workspace holds two sets of digit planes; panel g uses */
-                      /* set g % 2 in every call).  Same result, bit for bit.   */
-                      /* No effect on the FP64 path                             */
+  int32_t lookahead;  /* hsumma_lu: nonzero = factor the next panel while the  */
+                      /* rest of the trailing update runs on a second stream.   */
+                      /* Split forms: 1 = hsumma_run splits outer panel g + 1   */
+                      /* on a second stream while the products of panel g run   */
+                      /* (the workspace holds two sets of digit planes; panel g */
+                      /* uses set g % 2 in every call); 2 = the same, but the   */
+                      /* overlap is used only where one product launch has      */
+                      /* fewer work items than the device has CUs (where it     */
+                      /* pays; elsewhere the plain sequence runs).  Same        */
+                      /* result, bit for bit.  No effect on the FP64 path;      */
+                      /* other values are invalid                               */
   int32_t wgs_per_cu; /* persistent launches: workgroups per CU, at most what   */
                       /* fits; 0 => what fits.  Fewer leave room on every CU    */
                       /* for concurrent work (hsumma_lu's look-ahead)           */

@@ -438,7 +438,21 @@ int launch_range(hsumma_plan_t p, const double* A, int64_t lda, const double* B,
   return launch_panel_products(p, sa, C, ldc, k0, k1, zero_init, ws, stream);
 }
 
-bool uses_lookahead(hsumma_plan_t p) { return p->lookahead && p->outer_lo.size() > 2; }
+// Whether a call overlaps the splits with the products: a look-ahead plan
+// with more than one outer step; in the automatic mode (opts.lookahead = 2)
+// only where one product launch has fewer work items than the device has
+// CUs -- the split then runs on CUs the products leave idle, while where the
+// persistent product launch holds every CU (its workgroups cannot share a
+// CU with the split's) the overlap gained nothing and cost up to 1 %.
+int lookahead_for_call(hsumma_plan_t p, bool* on) {
+  *on = p->lookahead && p->outer_lo.size() > 2;
+  if (!*on || p->opts.lookahead != 2) return HSUMMA_OK;
+  int dev = 0, cus = 0;
+  HS_CHECK_HIP(hipGetDevice(&dev));
+  HS_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *on = (int64_t)p->items.size() < (int64_t)cus;
+  return HSUMMA_OK;
+}
 
 // The second stream and the events of a look-ahead plan, made on first use
 // (the caller holds the plan's mutex); the plan then stays on that device.
@@ -526,8 +540,8 @@ int run_lookahead(hsumma_plan_t p, const double* A, int64_t lda, const double* B
 // The whole product: the work-item table, then every outer step in order
 // (the first stores instead of accumulating).
 int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
-               double* C, int64_t ldc, void* ws, hipStream_t stream) {
-  if (uses_lookahead(p)) return run_lookahead(p, A, lda, B, ldb, C, ldc, ws, stream);
+               double* C, int64_t ldc, void* ws, hipStream_t stream, bool lookahead) {
+  if (lookahead) return run_lookahead(p, A, lda, B, ldb, C, ldc, ws, stream);
   int rc = prepare_items(p, ws, stream);
   if (rc) return rc;
   const int64_t nouter = (int64_t)p->outer_lo.size() - 1;
@@ -544,11 +558,13 @@ int run_direct(hsumma_plan_t p, const double* A, int64_t lda, const double* B, i
 // events are shared by the plan's calls, so those calls are serialised.
 int run_direct_call(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64_t ldb,
                     double* C, int64_t ldc, void* ws, hipStream_t s) {
-  if (!uses_lookahead(p)) return run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
-  std::lock_guard<std::mutex> lk(p->mu);
-  int rc = ensure_aux(p);
+  bool la = false;
+  int rc = lookahead_for_call(p, &la);
   if (rc) return rc;
-  return run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+  if (!la) return run_direct(p, A, lda, B, ldb, C, ldc, ws, s, false);
+  std::lock_guard<std::mutex> lk(p->mu);
+  if ((rc = ensure_aux(p))) return rc;
+  return run_direct(p, A, lda, B, ldb, C, ldc, ws, s, true);
 }
 
 // Whole product on an explicit workspace, direct or through the plan's graph.
@@ -561,10 +577,10 @@ int run_on(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64
   // second stream joins the capture through the events and is joined back
   // before it ends.
   std::lock_guard<std::mutex> lk(p->mu);
-  if (uses_lookahead(p)) {
-    int rc = ensure_aux(p);   // outside the capture
-    if (rc) return rc;
-  }
+  bool la = false;
+  int rc0 = lookahead_for_call(p, &la);
+  if (!rc0 && la) rc0 = ensure_aux(p);   // outside the capture
+  if (rc0) return rc0;
   int dev = 0;
   HS_CHECK_HIP(hipGetDevice(&dev));
   GraphKey key{A, lda, B, ldb, C, ldc, ws, (void*)s};
@@ -575,7 +591,7 @@ int run_on(hsumma_plan_t p, const double* A, int64_t lda, const double* B, int64
       p->have_graph = false;
     }
     HS_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, ws, s);
+    int rc2 = run_direct(p, A, lda, B, ldb, C, ldc, ws, s, la);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (rc2) {
@@ -673,6 +689,7 @@ int hsumma_plan(hsumma_plan_t* out, int64_t n, int32_t P, int32_t Q, int32_t G, 
     return invalid("unknown precision");
   if (o.nb < 0) return invalid("nb must be >= 0");
   if (o.wgs_per_cu < 0) return invalid("wgs_per_cu must be >= 0");
+  if (o.lookahead < 0 || o.lookahead > 2) return invalid("lookahead must be 0, 1 or 2");
   int I = 0, J = 0;
   if (!hs::factor_groups(P, Q, G, &I, &J))
     return invalid("G cannot be arranged as I x J groups with I | P and J | Q");

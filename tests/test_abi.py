@@ -281,6 +281,14 @@ def test_split_lookahead_doubles_the_panel_sets():
     f1 = hs.Plan(512, 2, 2, 4, 32, 128, lookahead=1)
     assert f1.workspace_size == f0.workspace_size
     f0.close(); f1.close()
+    # 2: the automatic mode (decided per call) needs the same workspace as 1
+    a1 = hs.Plan(512, 2, 2, 4, 32, 128, prec=hs.SPLIT_INT8, lookahead=1)
+    a2 = hs.Plan(512, 2, 2, 4, 32, 128, prec=hs.SPLIT_INT8, lookahead=2)
+    assert a2.workspace_size == a1.workspace_size
+    a1.close(); a2.close()
+    for bad in (-1, 3):
+        with pytest.raises(hs.HsummaError):
+            hs.Plan(512, 2, 2, 4, 32, 128, prec=hs.SPLIT_INT8, lookahead=bad)
 
 
 def test_lu_plans_validate_and_size_their_workspace():

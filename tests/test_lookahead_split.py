@@ -184,6 +184,26 @@ def test_lookahead_step_calls_use_set_of_the_panel(prec):
     ahead.close()
 
 
+@pytest.mark.parametrize("n,k", [(1024, 4096), (4096, 2048)])
+def test_lookahead_auto_equals_plain(n, k):
+    # lookahead = 2 overlaps only where one product launch has fewer work
+    # items than CUs (n = 1024: 128 items of 64 x 128; n = 4096: 2048); the
+    # result is the plain one either way
+    import torch
+    P, Q, G, b, M = 4, 4, 4, 256, 1024
+    _say("case lookahead auto n=%d k=%d" % (n, k))
+    A = dev(inputs.exponent_spread(n, k, 81, 2.0))
+    B = dev(inputs.exponent_spread(k, n, 82, 2.0))
+    plain = hs.Plan(n, P, Q, G, b, M, k=k, prec=hs.SPLIT_INT8)
+    auto = hs.Plan(n, P, Q, G, b, M, k=k, prec=hs.SPLIT_INT8, lookahead=2)
+    ref, _ = _run(plain, A, B)
+    got, _ = _run(auto, A, B)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    plain.close()
+    auto.close()
+
+
 def test_lookahead_noalloc():
     import torch
     n, P, Q, G, b, M = 640, 2, 2, 4, 32, 128
