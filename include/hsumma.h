@@ -25,7 +25,10 @@
  *
  * Ownership.  The caller owns A, B, C and the workspace `ws`: device memory
  * of at least hsumma_workspace_size() bytes, 256-byte aligned, required by
- * every compute call of every precision.  The library allocates no device
+ * every compute call of every precision.  4 KiB alignment is recommended:
+ * the split forms' digit planes start on 4 KiB boundaries of `ws`, and their
+ * product kernels ran 1-2 % slower with planes 256 or 1536 bytes off such a
+ * boundary in device memory.  The library allocates no device
  * memory and copies nothing from the host to the device: each compute call
  * first writes the plan's work-item table (the macro-tiles of every virtual
  * processor, see hsumma_work_items) into `ws` with a small kernel, then
@@ -327,7 +330,7 @@ int hsumma_mfma_exact_probe(int32_t fmt, const void* a, const void* b, int32_t k
  * No pivoting: the caller guarantees nonzero leading principal minors (e.g.
  * a diagonally dominant matrix); a zero pivot yields Inf or NaN in the
  * factors.  The plan is host memory; ws (hsumma_lu_workspace_size() bytes,
- * 256-byte aligned) holds the negated panel L21 (n x M doubles) and the
+ * 256-byte aligned, 4 KiB recommended as for hsumma_run) holds the negated panel L21 (n x M doubles) and the
  * trailing updates' workspace.  Asynchronous on `stream`.
  *
  * opts.lookahead = 1 overlaps the factorisation of each outer panel with the

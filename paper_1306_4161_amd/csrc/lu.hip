@@ -362,7 +362,9 @@ int hsumma_lu_plan(hsumma_lu_plan_t* out, int64_t n, int32_t P, int32_t Q, int32
       return rc;
     }
   }
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  // 4 KiB units: the trailing updates' own workspaces (digit planes of the
+  // split forms) then start on 4 KiB boundaries of a 4 KiB-aligned workspace
+  auto al = [](size_t x) { return (x + 4095) & ~(size_t)4095; };
   // the negated L21 panel: two buffers with look-ahead (the next panel is
   // written while the rest of the trailing update still reads this one)
   p->negL_bytes = al((size_t)n * (size_t)M * sizeof(double));

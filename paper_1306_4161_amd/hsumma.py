@@ -171,6 +171,19 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+WS_ALIGN = 4096   # workspace alignment the library recommends (256 is required)
+
+
+def _aligned_bytes(nbytes, device):
+    """A uint8 device tensor of nbytes starting on a WS_ALIGN boundary: a view
+    into a slightly larger allocation (the caching allocator may hand out
+    blocks at any 512-byte offset)."""
+    import torch
+    raw = torch.empty(nbytes + WS_ALIGN, dtype=torch.uint8, device=device)
+    start = (-raw.data_ptr()) % WS_ALIGN
+    return raw[start:start + nbytes]
+
+
 class Plan:
     """Host plan for C = A x B on a virtual P x Q grid with G groups."""
 
@@ -259,9 +272,9 @@ class Plan:
 
     # ---- compute ---------------------------------------------------------
     def workspace(self, device="cuda"):
-        """A device workspace of hsumma_workspace_size() bytes (torch owns it)."""
-        import torch
-        return torch.empty(self.workspace_size, dtype=torch.uint8, device=device)
+        """A device workspace of hsumma_workspace_size() bytes, 4 KiB-aligned
+        (torch owns it)."""
+        return _aligned_bytes(self.workspace_size, device)
 
     def _args(self, A, B, C, ws):
         a, lda = _dev_ptr(A, "A")
@@ -363,8 +376,8 @@ class LuPlan:
         return v.value
 
     def workspace(self, device="cuda"):
-        import torch
-        return torch.empty(self.workspace_size, dtype=torch.uint8, device=device)
+        """A device workspace of hsumma_lu_workspace_size() bytes, 4 KiB-aligned."""
+        return _aligned_bytes(self.workspace_size, device)
 
     def factor(self, A, ws, stream=None):
         """A = L U in place (A: n x n float64 CUDA tensor, row-major)."""

@@ -254,6 +254,18 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch_array():
     big.close()
 
 
+def test_digit_planes_start_on_4k_boundaries():
+    # the plane sets (and their partial statistics) sit on 4 KiB boundaries of
+    # the workspace, whatever the item table before them
+    for n, P, Q, G, b, M, prec in [(700, 3, 2, 2, 32, 96, hs.SPLIT_INT8),
+                                   (1000, 4, 4, 4, 64, 256, hs.SPLIT_BF16),
+                                   (333, 1, 3, 3, 16, 48, hs.SPLIT_FP8)]:
+        p = hs.Plan(n, P, Q, G, b, M, prec=prec)
+        lay = p.split_layout()
+        assert lay["off_digA"] % 4096 == 0 and lay["off_digB"] % 4096 == 0
+        p.close()
+
+
 def test_split_outer_block_fits_the_split_grid():
     # one grid row of the split kernels per 64 panel columns, at most 65535
     hs.Plan(64, 1, 1, 1, 64, 65535 * 64, k=65535 * 64, prec=hs.SPLIT_BF16).close()
@@ -274,7 +286,9 @@ def test_split_lookahead_doubles_the_panel_sets():
         part = 6 * (Wp // 64) * (m + n) * 8       # per-slab partial statistics
         extra = (al(planes * m * Wp * esz) + al(planes * n * Wp * esz) + al(4 * m) + al(4 * n)
                  + al(part))
-        assert ahead.workspace_size == plain.workspace_size + extra
+        # (up to three 4 KiB roundings: each plane set and the partial
+        # statistics start on a 4 KiB boundary)
+        assert 0 <= ahead.workspace_size - plain.workspace_size - extra <= 3 * 4096
         assert ahead.work_items().tolist() == plain.work_items().tolist()
         plain.close(); ahead.close()
     f0 = hs.Plan(512, 2, 2, 4, 32, 128)

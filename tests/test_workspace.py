@@ -111,3 +111,20 @@ def test_device_table_equals_host_definition_random_plans():
 
     _say("case random device tables")
     check()
+
+
+def test_workspace_helpers_return_4k_aligned_buffers():
+    # the bindings' workspace helpers honour the recommended 4 KiB alignment
+    # (the caching allocator alone hands out blocks at 512-byte offsets)
+    import torch
+    keep = [torch.empty(1536 + 512 * i, dtype=torch.uint8, device="cuda") for i in range(4)]
+    for prec in (hs.FP64, hs.SPLIT_INT8):
+        p = hs.Plan(640, 2, 2, 4, 32, 128, prec=prec)
+        for _ in range(3):
+            ws = p.workspace()
+            assert ws.data_ptr() % 4096 == 0 and ws.numel() == p.workspace_size
+        p.close()
+    lu = hs.LuPlan(512, 2, 2, 4, 32, 128)
+    assert lu.workspace().data_ptr() % 4096 == 0
+    lu.close()
+    del keep
