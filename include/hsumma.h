@@ -290,7 +290,8 @@ int hsumma_panel_slices(hsumma_plan_t plan, const void* ws, int32_t* counts, voi
  * Layout of the split forms' workspace after a call: byte offsets of the A
  * digit planes (planes x m x Wp digits, 2 B per BF16 digit or 1 B per
  * FP8-e4m3 or INT8 digit, stored k16-block-major: digit (plane, row, k) at
- * plane*m*Wp + (k/16)*m*16 + row*16 + k%16), the B digit planes (the same
+ * plane*m*Wp + (k/16)*m*16 + row*16 + k%16; INT8 k32-block-major, at
+ * plane*m*Wp + (k/32)*m*32 + row*32 + k%32), the B digit planes (the same
  * with n columns: B transposed), the int32 row exponents of A and column
  * exponents of B.  They hold the most recently split panel (with look-ahead:
  * the most recently split even outer panel; odd ones use a second set); of

@@ -117,11 +117,13 @@ __device__ inline uint8_t e4m3_of_int(int d) {
   return (uint8_t)(bits | (d < 0 ? 0x80 : 0));
 }
 
-// Digit planes are stored k16-block-major: element (plane, row, kk) at
-// plane * plane_stride + (kk / 16) * rows * 16 + row * 16 + kk % 16, so that
-// the 16 k of one row of one block are contiguous and one block of a plane
-// (all rows) is one contiguous run, the unit the product kernel streams.
-// INT8 digits are stored as their two's-complement bytes.
+// Digit planes are stored in k-blocks of the product kernel's step: BF16 and
+// FP8 k16-block-major, element (plane, row, kk) at plane * plane_stride +
+// (kk / 16) * rows * 16 + row * 16 + kk % 16; INT8 k32-block-major, at
+// plane * plane_stride + (kk / 32) * rows * 32 + row * 32 + kk % 32.  So the
+// k of one row in one step are contiguous and one step of a plane (all rows)
+// is one contiguous run, the unit the product kernel streams.  INT8 digits
+// are stored as their two's-complement bytes.
 
 // Slice count of a panel from its statistics.  ka, kb: log2 of the largest
 // kappa = max|x| w / sum|x| over the panel's A rows and B columns.  Model of
@@ -463,8 +465,11 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArg
   else if (line < nl) load_col_tile(p, line, k0, x);
   if (line >= nl) return;
   const int e = (rows ? p.eA : p.fB)[line];
-  // k16-block-major planes: (plane, line, kk) at plane * stride + (kk / 16) lines 16 + line 16 + kk % 16
-  const int64_t pos = (int64_t)(k0 >> 4) * ((int64_t)nl * 16) + (int64_t)line * 16;
+  // the tile's 16 digits per plane: k16-block-major (BF16, FP8), or half
+  // (k0 / 16) % 2 of the line's 32 bytes in k32 block k0 / 32 (INT8)
+  const int64_t pos = FMT == 2 ? (int64_t)(k0 >> 5) * ((int64_t)nl * 32) + (int64_t)line * 32 +
+                                     ((k0 >> 4) & 1) * 16
+                               : (int64_t)(k0 >> 4) * ((int64_t)nl * 16) + (int64_t)line * 16;
   uint8_t* dig = (uint8_t*)(rows ? p.digA : p.digB);
   const int64_t plane = rows ? p.planeA : p.planeB;
   static_for<1, kSplitMaxSlices + 1>([&](auto S) {
@@ -1071,10 +1076,11 @@ __global__ __launch_bounds__(256, 1) void slice_fp8_kernel(SliceArgs p) {
 // 16-k BF16 one from the same 16 bytes per lane, so it does twice the k per
 // clock; a 32-k step of a plane is the BF16 step's 64 x 32 bytes of A and
 // 128 x 32 bytes of B, with the same LDS image, swizzle, ring and DMA
-// deal over the waves.  The planes are stored k16-block-major (as the FP8
-// ones): a 32-k step kb is k16 blocks 2 kb (half 0) and 2 kb + 1 (half 1),
-// so the 16-byte unit (row, half) of the step sits at row x 16 + half x rows
-// x 16 past the step's base.  Every level of digit pairs stays exact in INT32
+// deal over the waves.  The planes are stored k32-block-major: the
+// 16-byte unit (row, half) of a 32-k step sits at row x 32 + half x 16 past
+// the step's base, so each DMA wave-instruction (32 rows or columns, both
+// halves) reads one contiguous 1 KB run (with k16 blocks it read two 512-byte
+// runs a k16 block apart).  Every level of digit pairs stays exact in INT32
 // over a whole panel (at most 8 pairs of |d d'| <= 2^14 per k, panels of at
 // most 8192 k), so each level keeps one accumulator from the item's first
 // step to its last, with no restarts, and the levels are added into FP64
@@ -1113,7 +1119,6 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
   const __amdgpu_buffer_rsrc_t rsrcB =
       __builtin_amdgcn_make_buffer_rsrc((void*)p.digB, (short)0, (int)p.bytesB, kBufferWord3);
   const uint32_t kbA = (uint32_t)p.rowsA * 32u, kbB = (uint32_t)p.rowsB * 32u;  // bytes per 32-k step
-  const uint32_t halfA = (uint32_t)p.rowsA * 16u, halfB = (uint32_t)p.rowsB * 16u;
   const uint32_t planeAB = (uint32_t)p.planeA, planeBB = (uint32_t)p.planeB;   // one byte per digit
   const int nsteps = p.Wp / 32;                // even: the panel is padded to 64 k
   // LDS byte offsets of this lane's A and B fragments (rows / columns
@@ -1144,8 +1149,8 @@ __device__ __forceinline__ void slice_i8_items(const SliceArgs& p, uint8_t* smem
     const int rowa = ua >> 1, halfa = (ua & 1) ^ ((rowa >> 3) & 1);
     const int ub = wave * 64 + l;
     const int colb = ub >> 1, halfb = (ub & 1) ^ ((colb >> 3) & 1);
-    voffA = (uint32_t)(w.r0 + min(rowa, w.h - 1)) * 16u + halfa * halfA;
-    voffB = (uint32_t)(w.c0 + min(colb, w.w - 1)) * 16u + halfb * halfB;
+    voffA = (uint32_t)(w.r0 + min(rowa, w.h - 1)) * 32u + halfa * 16u;
+    voffB = (uint32_t)(w.c0 + min(colb, w.w - 1)) * 32u + halfb * 16u;
   };
   auto dmaA = [&](int plane, int kb, uint8_t* dst) {
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrcA, (__attribute__((address_space(3))) void*)dst, 16,

@@ -118,11 +118,13 @@ def test_digit_planes_match_oracle_bitwise(prec, fmt):
     raw = ws.cpu().numpy()
     esz = 2 if fmt == "bf16" else 1
     dt = np.uint16 if esz == 2 else np.uint8
-    # planes are stored k16-block-major: [plane][k // 16][row][k % 16]
+    # planes are stored in k-blocks of the product kernel's step, [plane][k //
+    # kb][row][k % kb]: kb = 16 for BF16 and FP8, 32 for INT8
+    kb = 32 if fmt == "int8" else 16
     digA = raw[lay["off_digA"]: lay["off_digA"] + planes * m * Wp * esz].view(dt)
-    digA = digA.reshape(planes, Wp // 16, m, 16).transpose(0, 2, 1, 3).reshape(planes, m, Wp)
+    digA = digA.reshape(planes, Wp // kb, m, kb).transpose(0, 2, 1, 3).reshape(planes, m, Wp)
     digB = raw[lay["off_digB"]: lay["off_digB"] + planes * n * Wp * esz].view(dt)
-    digB = digB.reshape(planes, Wp // 16, n, 16).transpose(0, 2, 1, 3).reshape(planes, n, Wp)
+    digB = digB.reshape(planes, Wp // kb, n, kb).transpose(0, 2, 1, 3).reshape(planes, n, Wp)
     eA = raw[lay["off_eA"]: lay["off_eA"] + 4 * m].view(np.int32)
     fB = raw[lay["off_fB"]: lay["off_fB"] + 4 * n].view(np.int32)
     e_ref = split_ref.exponents(A, axis=1)
