@@ -453,23 +453,60 @@ __global__ __launch_bounds__(64 * kSplitWaves) void split_digits_kernel(SplitArg
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.slices_out = s;
   if (s == 0) return;                         // the FP64 kernel computes this panel
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int k0 = blockIdx.y * kSlabK + 16 * wave;
-  if (k0 >= p.Wp) return;                     // (FP8: a half slab at the end; no barrier follows)
   const int ga = (p.m + 63) / 64;
   const bool rows = (int)blockIdx.x < ga;
   const int blk = rows ? blockIdx.x : blockIdx.x - ga;
   const int nl = rows ? p.m : p.n;
-  const int line = blk * 64 + lane;
   double x[16];
-  if (rows) load_row_tile(p, blk, k0, tiles[wave], x);
-  else if (line < nl) load_col_tile(p, line, k0, x);
+  int line;
+  int64_t pos;
+  if constexpr (FMT == 2) {
+    // INT8 planes are k32-block-major: a wave takes 32 lines x one k32 block
+    // (lanes 0-31 its first 16 k, lanes 32-63 its second), so that each of
+    // its plane stores is one contiguous 1 KB run
+    const int l32 = lane & 31, half = lane >> 5;
+    const int first = blk * 64 + (wave & 1) * 32;   // the wave's first line
+    const int kb = blockIdx.y * 2 + (wave >> 1);     // k32 block (kb * 32 < Wp: Wp is a multiple of 64)
+    line = first + l32;
+    if (rows) {
+      // the 32 x 32 tile of rows [first, first + 32) (clamped) staged through
+      // this wave's LDS tile (row stride 34 doubles), 4 rows x 256 bytes per
+      // wave-load, then half `half` of row l32 into x
+      double* tile = tiles[wave];
+      const int lr = lane >> 4, kp = 2 * (lane & 15);
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int row = min(first + lr + 4 * i, p.m - 1);
+        const int kk = kb * 32 + kp;
+        const double* rp = p.A + (int64_t)row * p.lda + p.k0 + kk;
+        v[2 * i] = kk < p.w ? rp[0] : 0.0;
+        v[2 * i + 1] = kk + 1 < p.w ? rp[1] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        double* t = tile + (lr + 4 * i) * 34 + kp;
+        t[0] = v[2 * i];
+        t[1] = v[2 * i + 1];
+      }
+      // the same wave reads the tile back: its LDS accesses complete in order
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x[q] = tile[l32 * 34 + half * 16 + q];
+    } else if (line < nl) {
+      load_col_tile(p, line, kb * 32 + half * 16, x);
+    }
+    pos = (int64_t)kb * ((int64_t)nl * 32) + (int64_t)line * 32 + half * 16;
+  } else {
+    const int k0 = blockIdx.y * kSlabK + 16 * wave;
+    if (k0 >= p.Wp) return;                   // (FP8: a half slab at the end; no barrier follows)
+    line = blk * 64 + lane;
+    if (rows) load_row_tile(p, blk, k0, tiles[wave], x);
+    else if (line < nl) load_col_tile(p, line, k0, x);
+    // k16-block-major: (plane, line, kk) at (kk / 16) lines 16 + line 16 + kk % 16
+    pos = (int64_t)(k0 >> 4) * ((int64_t)nl * 16) + (int64_t)line * 16;
+  }
   if (line >= nl) return;
   const int e = (rows ? p.eA : p.fB)[line];
-  // the tile's 16 digits per plane: k16-block-major (BF16, FP8), or half
-  // (k0 / 16) % 2 of the line's 32 bytes in k32 block k0 / 32 (INT8)
-  const int64_t pos = FMT == 2 ? (int64_t)(k0 >> 5) * ((int64_t)nl * 32) + (int64_t)line * 32 +
-                                     ((k0 >> 4) & 1) * 16
-                               : (int64_t)(k0 >> 4) * ((int64_t)nl * 16) + (int64_t)line * 16;
   uint8_t* dig = (uint8_t*)(rows ? p.digA : p.digB);
   const int64_t plane = rows ? p.planeA : p.planeB;
   static_for<1, kSplitMaxSlices + 1>([&](auto S) {
