@@ -198,6 +198,44 @@ def test_equals_truncated_split_product(prec, fmt, s):
     assert np.all(np.abs(C[rows, cols] - T) <= tol)
 
 
+def test_bf16_deep_levels_round_within_their_bound():
+    # BF16 digit pairs of levels 4 and up (l1 + l2 >= 6) share one FP32
+    # accumulator, which rounds; INT8 keeps every level exact.  A wide spread
+    # (sigma = 3, k = 1024) with the slice count fixed, so that the panel is
+    # split rather than sent to the FP64 kernel, against the oracle's exact
+    # truncated product T of the same digits: INT8 within the FP64 additions'
+    # bound, BF16 within that plus the deep accumulator's stated estimate
+    # 2^-60.5 kappa_A kappa_B / sqrt(k) of (|A||B|)_ij (kappa = max|x| w /
+    # sum|x| of the worst line), with a factor 16 of margin on the estimate
+    # (measured: INT8 2.0e-16, BF16 9.5e-14 -- above the FP64 additions'
+    # bound, so the deep rounding shows -- against an estimate of 1.0e-14).
+    _say("case BF16 deep levels sigma=3")
+    m, k, n, M = 96, 1024, 80, 1024
+    A = inputs.exponent_spread(m, k, 151, sigma=3.0)
+    B = inputs.exponent_spread(k, n, 152, sigma=3.0)
+    rows, cols = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    rows, cols = rows.ravel()[::2], cols.ravel()[::2]
+    S = (np.abs(A) @ np.abs(B))[rows, cols]
+    nadd = 8 * (k // 32 + 2) + 4 * (k // M + 1)
+    kA = np.max(np.max(np.abs(A), axis=1) * k / np.sum(np.abs(A), axis=1))
+    kB = np.max(np.max(np.abs(B), axis=0) * k / np.sum(np.abs(B), axis=0))
+    deep = 16 * 2.0 ** -60.5 * kA * kB / np.sqrt(k)
+    for prec, fmt, s in ((hs.SPLIT_INT8, "int8", 8), (hs.SPLIT_BF16, "bf16", 7)):
+        p = hs.Plan(n, 2, 2, 2, 64, M, m=m, k=k, prec=prec, slices=s, min_slices=1)
+        C, ws = _run(p, A, B)
+        assert p.panel_slices(ws) == [s]
+        T = split_ref.truncated_entries(A, B, M, s, fmt, rows, cols)
+        err = np.abs(C[rows, cols] - T)
+        tol = nadd * core.U * (S + np.abs(T))
+        _say("  %s s=%d: max |C - T| / (|A||B|) %.3g (FP64 additions' bound %.3g, deep "
+             "estimate with margin %.3g)" % (fmt, s, np.max(err / S), np.max(tol / S), deep))
+        if fmt == "int8":
+            assert np.all(err <= tol)
+        else:
+            assert np.all(err <= tol + deep * S)
+        p.close()
+
+
 @pytest.mark.parametrize("prec,fmt,s", [(hs.SPLIT_INT8, "int8", 8), (hs.SPLIT_BF16, "bf16", 7)])
 def test_truncated_product_with_many_items_per_workgroup(prec, fmt, s):
     # 2000 x 1900 with 64 x 128 macro-tiles is 32 x 15 = 480 items, so most
