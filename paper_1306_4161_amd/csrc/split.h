@@ -10,7 +10,8 @@ constexpr int kSplitMaxSlices = 8;   // digit planes written per operand (any fo
 constexpr int split_max_slices(int fmt) { return fmt == 2 ? 8 : 7; }
 constexpr int kSplitChunk = 32;      // panel width is padded to a multiple of this
 
-// Per-panel statistics written by the statistics pass (uint32 words):
+// Per-panel statistics (uint32 words): the non-finite flag written by the
+// statistics kernel, the maxima by the combine kernel:
 constexpr int kStatKappaA = 0;       // max over A rows of log2 kappa (float bits)
 constexpr int kStatKappaB = 1;       // max over B columns of log2 kappa (float bits)
 constexpr int kStatCohA = 2;         // max over A rows of the residual coherence (float bits)
@@ -29,7 +30,7 @@ struct SplitArgs {
   void* digA; int64_t planeA;        // planes of m x Wp digits (elements per plane)
   void* digB; int64_t planeB;        // planes of n x Wp digits (B transposed)
   int32_t* eA; int32_t* fB;          // per-row / per-column exponents
-  uint32_t* stats;                   // kStatWords words, cleared before the statistics pass
+  uint32_t* stats;                   // kStatWords words, cleared before the statistics kernel
   double* part;                      // per-slab partial sums of every line (split_part_doubles)
   int32_t nslab;                     // 64-k slabs of the padded panel: ceil(Wp / 64)
   int32_t* slices_out;               // the panel's slice count (0: the FP64 kernel computes it)
@@ -43,7 +44,7 @@ struct SliceArgs {
   const void* digB; int64_t planeB; int32_t rowsB;   // rowsB = n
   uint32_t bytesA, bytesB;           // byte sizes of the two digit regions (< 4 GiB)
   const int32_t* eA; const int32_t* fB;
-  const int32_t* slices;             // the panel's slice count, written by the digit pass
+  const int32_t* slices;             // the panel's slice count, written by the digit kernel
                                      // (0: the launch does nothing)
   double* C; int64_t ldc;
   const WorkItem* items; int32_t nitems; int32_t per_xcd;
