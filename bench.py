@@ -26,7 +26,7 @@ workload.
 dominant kernel: c1 (n = 8192, 8 x 8 grid, G = 4, M = 256, b = 64, FP64),
 c3 (n = 10000 on a 6 x 10 block-cyclic grid, b = M = 128, one grouped
 persistent launch per step over the 60 uneven tiles, replayed as a HIP
-graph; FP64 and the INT8 split), lu (n = 16384 LU without pivoting,
+graph; FP64 and the INT8 and BF16 splits), lu (n = 16384 LU without pivoting,
 16 x 16 grid, G = 16: the trailing updates are HSUMMA outer updates) and la
 (the split forms with and without look-ahead, m = n = 1024, k = 65536,
 where one product launch fills half the CUs).
@@ -230,7 +230,8 @@ def bench_workloads(names, args, stream):
             n, P, Q, b = 10000, 6, 10, 128
             dA, dB = gpu_uniform((n, n), 2013), gpu_uniform((n, n), 4161)
             dC = torch.empty((n, n), dtype=torch.float64, device="cuda")
-            for prec, name in ((hs.FP64, "c3_fp64"), (hs.SPLIT_INT8, "c3_int8")):
+            for prec, name in ((hs.FP64, "c3_fp64"), (hs.SPLIT_INT8, "c3_int8"),
+                               (hs.SPLIT_BF16, "c3_bf16")):
                 plan = hs.Plan(n, P, Q, 1, b, dist=hs.DIST_BLOCK_CYCLIC, prec=prec,
                                persistent=1, use_graph=1)
                 ws = plan.workspace()
@@ -259,10 +260,13 @@ def bench_workloads(names, args, stream):
                     per_launch = pairs * 2.0 * n * n * b
                     ach = per_launch / (pms * 1e-3) / 1e12
                     rec.update({"slices": sorted(set(sl)), "pairs": pairs})
+                    i8 = prec == hs.SPLIT_INT8
                     rec["roofline"] = {"bound": "mfma", "achieved": round(ach, 2),
-                                       "peak": PEAK_INT8, "unit": "TOP/s",
-                                       "frac": round(ach / PEAK_INT8, 4),
-                                       "kernel": "slice_i8_kernel", "flops_per_launch": per_launch,
+                                       "peak": PEAK_INT8 if i8 else PEAK_BF16,
+                                       "unit": "TOP/s" if i8 else "TFLOP/s",
+                                       "frac": round(ach / (PEAK_INT8 if i8 else PEAK_BF16), 4),
+                                       "kernel": "slice_i8_kernel" if i8 else "slice_bf16_kernel",
+                                       "flops_per_launch": per_launch,
                                        "avg_launch_ms": round(pms, 4)}
                 out[name] = rec
                 log("%s: %.3f ms/step, %.1f GFLOP/s" % (name, ms, rec["gflops"]))
